@@ -1,0 +1,440 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the identity it checks and the passage of the paper (Freericks,
+arXiv:0711.0999, Sec. II) that fixes it.  None of them re-types the oracle's own
+formula: they compare it with closed forms, special cases that reduce to a
+textbook or library result, invariants, or a high-precision brute force.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import contour, green, impurity, lattice, quadrature, dmft
+
+
+# ----------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("n", [1, 2, 5, 10, 35, 55])
+def test_gauss_hermite_matches_library(n):
+    """Gauss-Hermite rule for the Gaussian DOS of eq. (joint_dos): nodes and
+    normalized weights equal numpy's hermgauss (weights / sqrt(pi))."""
+    x, w = quadrature.hermite_rule(n)
+    xl, wl = np.polynomial.hermite.hermgauss(n)
+    assert np.max(np.abs(x - xl)) < 1e-12 * max(1.0, np.max(np.abs(xl)))
+    assert np.max(np.abs(w - wl / math.sqrt(math.pi))) < 1e-14
+    assert abs(w.sum() - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("n", [3, 10, 55])
+def test_gauss_hermite_moments_exact(n):
+    """Gaussian moments int x^{2m} e^{-x^2} dx / sqrt(pi) = (2m-1)!!/2^m are
+    integrated exactly for 2m <= 2n - 1."""
+    x, w = quadrature.hermite_rule(n)
+    for m in range(0, min(n, 8)):
+        exact = float(np.prod(np.arange(1, 2 * m, 2))) / 2.0 ** m
+        got = float(np.sum(w * x ** (2 * m)))
+        assert abs(got - exact) < 1e-12 * max(1.0, exact)
+        assert abs(float(np.sum(w * x ** (2 * m + 1)))) < 1e-12 * max(1.0, exact)
+
+
+def test_product_grid_weights_sum_to_one():
+    eps, ebar, rho = quadrature.product_grid(10, 7)
+    assert eps.shape == ebar.shape == rho.shape == (70,)
+    assert abs(rho.sum() - 1.0) < 1e-14
+    # k = a * n_ebar + b
+    x10, _ = quadrature.hermite_rule(10)
+    x7, _ = quadrature.hermite_rule(7)
+    assert eps[3 * 7 + 5] == x10[3] and ebar[3 * 7 + 5] == x7[5]
+
+
+# -------------------------------------------------------------------- contour
+def test_contour_branch_endpoints():
+    """Sec. II: the upper branch runs t_min .. t_max - dt, the lower t_max ..
+    t_min + dt, the imaginary one t_min .. t_min - i beta + i dtau."""
+    z, w = contour.points(-5.0, 5.0, 0.2, 0.2, 10.0)
+    n_t, n_tau, n_c = contour.sizes(-5.0, 5.0, 0.2, 0.2, 10.0)
+    assert (n_t, n_tau, n_c) == (50, 50, 150)
+    assert z[0] == -5.0 and abs(z[n_t - 1] - 4.8) < 1e-12
+    assert z[n_t] == 5.0 and abs(z[2 * n_t - 1] - (-4.8)) < 1e-12
+    assert z[2 * n_t] == -5.0 and abs(z[-1] - complex(-5.0, -9.8)) < 1e-12
+    # leftpoint rule: the real branches cancel, the imaginary one gives -i beta
+    assert abs(w[:2 * n_t].sum()) < 1e-12
+    assert abs(w[2 * n_t:].sum() - complex(0, -10.0)) < 1e-12
+    with pytest.raises(ValueError):
+        contour.sizes(-5.0, 5.0, 0.3, 0.2, 10.0)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3, -0.7])
+def test_det_m_partition_function(mu):
+    """eq. (det): det M is the partition function of a spinless level.  The
+    discrete value is 1 + prod_j (1 + i W_j mu) = 1 + (1 + dt^2 mu^2)^{N_t}
+    (1 + dtau mu)^{N_tau} (the printed sign prefactor is taken as a misprint),
+    and it tends to 1 + e^{beta mu} as dt, dtau -> 0."""
+    t_min, t_max, beta = -5.0, 5.0, 10.0
+    errs = []
+    for dt in (0.2, 0.1, 0.05):
+        z, w = contour.points(t_min, t_max, dt, dt, beta)
+        n_t, n_tau, _ = contour.sizes(t_min, t_max, dt, dt, beta)
+        det = np.linalg.det(contour.m_matrix(w, mu))
+        closed = 1.0 + (1.0 + dt * dt * mu * mu) ** n_t * (1.0 + dt * mu) ** n_tau
+        assert abs(det - closed) < 1e-9 * abs(closed)
+        errs.append(abs(det - (1.0 + math.exp(beta * mu))) / (1.0 + math.exp(beta * mu)))
+    if mu != 0.0:
+        assert errs[0] > errs[1] > errs[2]
+        assert errs[1] / errs[2] > 1.6   # first order in dt
+    else:
+        assert max(errs) < 1e-12
+
+
+def test_shift_operator_is_point_split_identity():
+    """i W^-1 (M(mu') - M(mu)) = (mu' - mu) S with S the point-split delta:
+    S[j, j-1] = +1 and the antiperiodic corner S[0, N-1] = -1."""
+    z, w = contour.points(-1.0, 1.0, 0.2, 0.25, 1.0)
+    n = len(w)
+    s = np.zeros((n, n), dtype=np.complex128)
+    s[np.arange(1, n), np.arange(n - 1)] = 1.0
+    s[0, n - 1] = -1.0
+    got = contour.shift_operator(w, 0.4, 0.4 - 0.75)
+    assert np.max(np.abs(got - (-0.75) * s)) < 1e-14
+
+
+# ---------------------------------------------------------------- noninteracting
+def test_g0_is_inverse_of_paper_operator_at_zero_energy():
+    """At eps = ebar = mu = 0 the sampled G0 of eq. (g_contour_non_final2) with
+    theta_c(t, t) = 1 is exactly the inverse of the paper's discrete operator
+    W [i d/dt] delta W = i M (the M display at mu = 0); theta_c(t, t) = 0 would
+    fail this."""
+    for (a, b, dt, dtau, beta) in [(-1.0, 1.0, 0.2, 0.2, 1.0), (-5.0, 5.0, 0.2, 0.2, 10.0)]:
+        z, w = contour.points(a, b, dt, dtau, beta)
+        n_t, _, _ = contour.sizes(a, b, dt, dtau, beta)
+        g0 = green.g0_matrix(z, n_t, 1.0, 0.0, beta, 0.0, 0.0)
+        ref = np.linalg.inv(1j * contour.m_matrix(w, 0.0))
+        assert np.max(np.abs(g0 - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("eps,ebar,mu,efield", [
+    (0.3, -0.8, 0.0, 1.0), (-3.1, 2.2, 0.0, 2.0), (7.5, 0.1, 0.2, 0.5),
+    (-9.2, -4.0, 0.0, 4.0), (1.1, 1.7, -0.3, 0.0)])
+def test_g0_inverse_is_bidiagonal_plus_corner(eps, ebar, mu, efield):
+    """The sampled G0 = i D (f 1 1^T - Theta) D^-1 with D = diag(e^{-i phi + i mu z})
+    and Theta the lower triangle including the diagonal.  Sherman-Morrison on
+    Theta - f 1 1^T gives the exact sparse inverse
+        G0^-1 = i D [I - P + e^{-beta (eps - mu)} e_0 e_{N-1}^T] D^-1
+    (P the unit subdiagonal).  A wrong phase sign, occupation or diagonal
+    convention in the generator makes the numerical inverse dense."""
+    beta = 10.0
+    z, w = contour.points(-2.0, 3.0, 0.1, 0.25, beta)
+    n_t, _, n_c = contour.sizes(-2.0, 3.0, 0.1, 0.25, beta)
+    g0 = green.g0_matrix(z, n_t, efield, mu, beta, eps, ebar)
+    inv = np.linalg.inv(g0)
+    # closed form built from the antiderivative evaluated independently here
+    t = z.real
+    alpha = z.copy()
+    gamma = np.zeros(n_c, dtype=np.complex128)
+    if efield != 0.0:
+        on = (np.arange(n_c) < 2 * n_t) & (t > 0)
+        alpha[on] = np.sin(efield * t[on]) / efield
+        gamma[on] = -2.0 * np.sin(0.5 * efield * t[on]) ** 2 / efield
+    ex = -1j * (eps * alpha + ebar * gamma) + 1j * mu * z
+    ref = np.zeros((n_c, n_c), dtype=np.complex128)
+    ref[np.arange(n_c), np.arange(n_c)] = 1j
+    ref[np.arange(1, n_c), np.arange(n_c - 1)] = -1j * np.exp(ex[1:] - ex[:-1])
+    ref[0, n_c - 1] = 1j * np.exp(-beta * (eps - mu) + ex[0] - ex[-1])
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(inv - ref)) < 1e-10 * scale
+    # |G0| <= 1 entrywise (bounded generator)
+    assert np.max(np.abs(g0)) <= 1.0 + 1e-12
+
+
+def test_u0_bloch_oscillation_closed_form():
+    """U = 0 (Sec. III: undamped Bloch oscillations).  With Sigma = 0 the
+    lesser function at equal times is i f(eps - mu) at every k, so n(t) =
+    sum_a w_a f(x_a - mu) (= 1/2 at mu = 0), and with the velocity at the
+    shifted momentum j(t) = -K sin(E t) theta(t), K = sum_a w_a x_a f(x_a - mu),
+    exactly at any dt.  The period is 2 pi / E."""
+    p = dmft.Problem(t_min=-5.0, t_max=5.0, dt=0.2, dtau=0.2, beta=10.0,
+                     u=0.0, e_field=1.0, n_eps=10, n_ebar=10)
+    z, w, n_t, eps, ebar, rho = p.grid()
+    n_c = len(z)
+    gloc, cur, _ = dmft.lattice_only(p, np.zeros((n_c, n_c), dtype=np.complex128))
+    x, wa = np.polynomial.hermite.hermgauss(10)
+    wa = wa / math.sqrt(math.pi)
+    f = 1.0 / (1.0 + np.exp(10.0 * x))
+    kin = float(np.sum(wa * x * f))
+    assert kin < 0.0
+    t = z[:n_t].real
+    expect = np.where(t > 0, -kin * np.sin(1.0 * t), 0.0)
+    assert np.max(np.abs(cur - expect)) < 1e-13
+    assert np.max(np.abs(lattice.density(gloc, n_t) - 0.5)) < 1e-13
+    # impurity update returns Sigma = 0 at U = 0
+    s_new = impurity.update(gloc, np.zeros_like(gloc), w, 0.0, 0.0, 0.5)
+    assert np.max(np.abs(s_new)) < 1e-9
+
+
+@pytest.mark.parametrize("efield", [0.5, 2.0])
+def test_retarded_gaussian_average(efield):
+    """First lattice step from Sigma = 0: G^R_loc(t, t') = G^> - G^< =
+    -i <exp(-i eps da - i ebar dg)>_rho = -i exp(-(da^2 + dg^2)/4) for t > t',
+    the characteristic function of the Gaussian DOS of eq. (joint_dos), with
+    da, dg the differences of sin(E t)/E and (cos(E t) - 1)/E (t > 0) or t."""
+    p = dmft.Problem(t_min=-2.0, t_max=4.0, dt=0.1, dtau=0.2, beta=4.0, u=0.0,
+                     e_field=efield, n_eps=20, n_ebar=20)
+    z, w, n_t, eps, ebar, rho = p.grid()
+    gl, _, _ = dmft.lattice_only(p, np.zeros((len(z),) * 2, dtype=np.complex128))
+    t = z[:n_t].real
+    a = np.where(t > 0, np.sin(efield * t) / efield, t)
+    g = np.where(t > 0, (np.cos(efield * t) - 1.0) / efield, 0.0)
+    worst = 0.0
+    for i in range(n_t):
+        for j in range(i):
+            gr = gl[2 * n_t - i if i else 2 * n_t, j] - gl[i, 2 * n_t - j if j else 2 * n_t]
+            ex = -1j * math.exp(-((a[i] - a[j]) ** 2 + (g[i] - g[j]) ** 2) / 4.0)
+            worst = max(worst, abs(gr - ex))
+    assert worst < 1e-10
+
+
+# -------------------------------------------------------------------- impurity
+def _lattice_gloc(u=1.0, efield=1.0):
+    p = dmft.Problem(t_min=-1.0, t_max=1.0, dt=0.2, dtau=0.25, beta=2.0, u=u,
+                     e_field=efield, n_eps=4, n_ebar=4)
+    z, w, n_t, eps, ebar, rho = p.grid()
+    rng = np.random.default_rng(5)
+    n = len(z)
+    sig = 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    gl, _, _ = dmft.lattice_only(p, sig)
+    return gl, sig, w
+
+
+def test_impurity_empty_and_full_f_site():
+    """eq. (g_imp_solve) with <w1> = 0 or 1 is a single level in a static
+    potential, so Sigma is that potential whatever G_loc and Sigma were:
+    Sigma W = -(mu0 - mu) S for w1 = 0 and -(mu1 - mu) S for w1 = 1 (S the
+    point-split delta).  Symmetric convention: -U/2 and +U/2; the paper's
+    literal convention: 0 and +U."""
+    gl, sig, w = _lattice_gloc()
+    n = len(w)
+    s = np.zeros((n, n), dtype=np.complex128)
+    s[np.arange(1, n), np.arange(n - 1)] = 1.0
+    s[0, n - 1] = -1.0
+    u = 1.3
+    for w1, conv, expect in [(0.0, "symmetric", -0.5 * u), (1.0, "symmetric", 0.5 * u),
+                             (0.0, "paper", 0.0), (1.0, "paper", u)]:
+        got = impurity.update(gl, sig, w, 0.0, u, w1, conv) * w[None, :]
+        assert np.max(np.abs(got - expect * s)) < 1e-9, (w1, conv)
+
+
+def test_impurity_u0_returns_zero():
+    gl, sig, w = _lattice_gloc()
+    got = impurity.update(gl, sig, w, 0.0, 0.0, 0.5)
+    assert np.max(np.abs(got)) < 1e-8
+
+
+# ------------------------------------------------------------------- lattice
+def test_static_sigma_shifts_chemical_potential():
+    """A static potential V enters Dyson's equation as Sigma = V delta, i.e.
+    Sigma W = V S point-split; the lattice then describes free electrons at
+    mu - V, so n(t) -> sum_a w_a f(x_a - mu + V) with an O(dt) error.  This
+    fixes the weighting of both contour integrals in eq. (dyson): a single W
+    leaves an O(1/dt) error."""
+    v = 0.3
+    errs = []
+    for dt in (0.2, 0.1, 0.05):
+        p = dmft.Problem(t_min=-1.0, t_max=1.0, dt=dt, dtau=dt, beta=2.0,
+                         u=0.0, e_field=0.0, n_eps=8, n_ebar=1)
+        z, w, n_t, eps, ebar, rho = p.grid()
+        n = len(z)
+        s = np.zeros((n, n), dtype=np.complex128)
+        s[np.arange(1, n), np.arange(n - 1)] = 1.0
+        s[0, n - 1] = -1.0
+        sigma = v * s / w[None, :]
+        gl, _, _ = dmft.lattice_only(p, sigma)
+        x, wa = quadrature.hermite_rule(8)
+        exact = float(np.sum(wa / (1.0 + np.exp(2.0 * (x + v)))))
+        errs.append(np.max(np.abs(lattice.density(gl, n_t) - exact)))
+    assert errs[0] < 0.1
+    assert errs[0] / errs[1] > 1.6 and errs[1] / errs[2] > 1.6
+
+
+def test_equilibrium_reduces_to_one_dimension():
+    """E = 0 (eq. joint_dos remark): nothing depends on ebar, so the 2-D sum
+    equals the 1-D sum over eps and the current vanishes."""
+    rng = np.random.default_rng(3)
+    base = dict(t_min=-1.0, t_max=1.0, dt=0.2, dtau=0.2, beta=2.0, u=1.0, e_field=0.0, n_eps=6)
+    p1 = dmft.Problem(n_ebar=1, **base)
+    p5 = dmft.Problem(n_ebar=5, **base)
+    n = len(p1.grid()[0])
+    sig = 0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    g1, c1, _ = dmft.lattice_only(p1, sig)
+    g5, c5, _ = dmft.lattice_only(p5, sig)
+    assert np.max(np.abs(g1 - g5)) < 1e-13
+    assert np.max(np.abs(c5)) < 1e-13
+
+
+def test_equilibrium_fixed_point_is_time_translation_invariant():
+    """At E = 0 the converged G_loc on the upper branch depends only on
+    t - t' (the equilibrium state of the Keldysh boundary problem)."""
+    p = dmft.Problem(t_min=-2.0, t_max=2.0, dt=0.2, dtau=0.2, beta=3.0, u=1.0,
+                     e_field=0.0, n_eps=6, n_ebar=1)
+    r = dmft.run(p, 60, tol=1e-12)
+    assert r["deltas"][-1] < 1e-12
+    g, n_t = r["gloc"], r["n_t"]
+    d = max(abs(g[i + 1, j + 1] - g[i, j]) for i in range(n_t - 1) for j in range(n_t - 1))
+    assert d < 1e-11
+    assert np.max(np.abs(r["current"])) < 1e-13
+
+
+def test_lattice_inverse_form_agrees():
+    """G_k = (I - G0 Sigma_t)^-1 G0 equals (G0^-1 - Sigma_t)^-1 (operator
+    Dyson equation G^-1 = G0^-1 - Sigma with the inverse rule of eq.
+    (matrix_inverse_discrete)) and satisfies the right-hand Dyson equation
+    G = G0 + G Sigma_t G0 as well."""
+    p = dmft.Problem(t_min=-1.0, t_max=2.0, dt=0.1, dtau=0.25, beta=2.0, u=1.0,
+                     e_field=1.5, n_eps=3, n_ebar=3)
+    z, w, n_t, eps, ebar, rho = p.grid()
+    n = len(z)
+    rng = np.random.default_rng(11)
+    sig = 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    st = lattice.weighted_sigma(sig, w)
+    for k in range(len(eps)):
+        gk = lattice.point_green(z, n_t, p.e_field, 0.0, p.beta, eps[k], ebar[k], st)
+        g0 = green.g0_matrix(z, n_t, p.e_field, 0.0, p.beta, eps[k], ebar[k])
+        alt = np.linalg.inv(np.linalg.inv(g0) - st)
+        assert np.max(np.abs(gk - alt)) < 1e-11 * np.max(np.abs(gk))
+        assert np.max(np.abs(gk - (g0 + gk @ st @ g0))) < 1e-11 * np.max(np.abs(gk))
+
+
+def test_convergence_order_of_invariants():
+    """U > 0 invariants that hold only in the continuum (Sec. III moments
+    paragraph and the extrapolation paragraph): n(t) = 1/2 at half filling, the
+    zeroth moment G^> - G^< = -i, and j(t < 0) = 0.  Their errors must shrink
+    about linearly as dt = dtau halves."""
+    res = []
+    for dt in (0.2, 0.1, 0.05):
+        p = dmft.Problem(t_min=-2.0, t_max=2.0, dt=dt, dtau=dt, beta=4.0, u=1.0,
+                         e_field=1.0, n_eps=6, n_ebar=6)
+        r = dmft.run(p, 80, tol=1e-10)
+        n_t = r["n_t"]
+        t = r["z"][:n_t].real
+        res.append((np.max(np.abs(r["density"] - 0.5)),
+                    np.max(np.abs(r["m0"] + 1j)),
+                    np.max(np.abs(r["current"][t < 0]))))
+    for q in range(3):
+        e = [x[q] for x in res]
+        assert e[0] > e[1] > e[2], (q, e)
+        assert e[1] / e[2] > 1.5, (q, e)
+
+
+# ------------------------------------------------------------ brute force
+def test_mpmath_brute_force_one_iteration():
+    """One full iteration (lattice step + impurity update) on a 12-point contour
+    with a 2 x 2 rule, evaluated at 40 digits from the same discrete equations
+    with mpmath: bounds the rounding of the complex128 oracle."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    t_min, t_max, dt, dtau, beta = -0.4, 0.4, 0.2, 0.2, 0.8
+    u, efield, w1 = 1.0, 1.0, 0.5
+    p = dmft.Problem(t_min=t_min, t_max=t_max, dt=dt, dtau=dtau, beta=beta,
+                     u=u, e_field=efield, n_eps=2, n_ebar=2)
+    z, w, n_t, eps, ebar, rho = p.grid()
+    n = len(z)
+    rng = np.random.default_rng(2)
+    sig0 = 0.2 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    r = dmft.run(p, 1, sigma0=sig0)
+
+    mpc = mp.mpc
+    zs = []
+    ws = []
+    for j in range(n):
+        if j < n_t:
+            zs.append(mpc(mp.mpf(t_min) + j * mp.mpf(dt))); ws.append(mpc(mp.mpf(dt)))
+        elif j < 2 * n_t:
+            zs.append(mpc(mp.mpf(t_max) - (j - n_t) * mp.mpf(dt))); ws.append(mpc(-mp.mpf(dt)))
+        else:
+            zs.append(mpc(mp.mpf(t_min), -(j - 2 * n_t) * mp.mpf(dtau))); ws.append(mpc(0, -mp.mpf(dtau)))
+    # 2-point Gauss-Hermite: nodes +-1/sqrt(2), normalized weights 1/2
+    nodes = [-1 / mp.sqrt(2), 1 / mp.sqrt(2)]
+    wts = [mp.mpf(1) / 2, mp.mpf(1) / 2]
+    sig = mp.matrix(n, n)
+    for i in range(n):
+        for j in range(n):
+            sig[i, j] = mpc(float(sig0[i, j].real), float(sig0[i, j].imag))
+    sig_t = mp.matrix(n, n)
+    for i in range(n):
+        for j in range(n):
+            sig_t[i, j] = ws[i] * sig[i, j] * ws[j]
+
+    def phi(j, e, eb):
+        zz = zs[j]
+        if j < 2 * n_t and mp.re(zz) > 0:
+            tt = mp.re(zz)
+            return e * mp.sin(efield * tt) / efield + eb * (mp.cos(efield * tt) - 1) / efield
+        return e * zz
+
+    gl = mp.matrix(n, n)
+    for a in range(2):
+        for b in range(2):
+            e, eb = nodes[a], nodes[b]
+            f = 1 / (1 + mp.exp(beta * e))
+            g0 = mp.matrix(n, n)
+            for i in range(n):
+                for j in range(n):
+                    occ = f - (1 if i >= j else 0)
+                    g0[i, j] = 1j * occ * mp.exp(-1j * (phi(i, e, eb) - phi(j, e, eb)))
+            gk = (mp.eye(n) - g0 * sig_t) ** -1 * g0
+            gl += wts[a] * wts[b] * gk
+    assert max(abs(complex(gl[i, j]) - r["gloc"][i, j]) for i in range(n) for j in range(n)) < 1e-12
+
+    gr = mp.matrix(n, n)
+    sr = mp.matrix(n, n)
+    shift = mp.matrix(n, n)
+    for i in range(n):
+        for j in range(n):
+            gr[i, j] = gl[i, j] * ws[j]
+            sr[i, j] = sig[i, j] * ws[j]
+    for j in range(1, n):
+        shift[j, j - 1] = 1
+    shift[0, n - 1] = -1
+    g0inv = gr ** -1 + sr
+    gimp = (1 - w1) * (g0inv + (u / 2) * shift) ** -1 + w1 * (g0inv - (u / 2) * shift) ** -1
+    snew = g0inv - gimp ** -1
+    worst = 0.0
+    for i in range(n):
+        for j in range(n):
+            worst = max(worst, abs(complex(snew[i, j] / ws[j]) - r["sigma"][i, j]))
+    assert worst < 1e-10 * max(1.0, float(np.max(np.abs(r["sigma"]))))
+
+
+def test_c1_reference_delta_history():
+    """C1 (t in [-5, 5], dt = dtau = 0.2, beta = 10, U = 0.5, E = 1, 10 x 10
+    rule, Sigma = 0): plain substitution contracts; ten iterations bring the
+    change of G_loc to ~5e-8."""
+    p = dmft.Problem(t_min=-5.0, t_max=5.0, dt=0.2, dtau=0.2, beta=10.0,
+                     u=0.5, e_field=1.0, n_eps=10, n_ebar=10)
+    r = dmft.run(p, 10)
+    d = r["deltas"]
+    assert len(d) == 10
+    assert all(d[i + 1] < d[i] for i in range(1, 9))
+    assert 1e-8 < d[-1] < 1e-7
+
+
+def test_impurity_second_order_perturbation():
+    """Weak coupling of eq. (g_imp_solve): expanding both resolvents in the
+    shifts +-U/2 gives the textbook Falicov-Kimball result
+        Sigma = U (w1 - 1/2) delta + U^2 w1 (1 - w1) G0_eff + O(U^3),
+    with G0_eff = [G_loc^-1 + Sigma]^-1 of eq. (effective_medium) and delta the
+    point-split S.  Checks the effective medium (including the +Sigma term) and
+    the mixing weights; the remainder must fall as U^3."""
+    gl, sig, w = _lattice_gloc()
+    n = len(w)
+    s = np.zeros((n, n), dtype=np.complex128)
+    s[np.arange(1, n), np.arange(n - 1)] = 1.0
+    s[0, n - 1] = -1.0
+    g_r = gl * w[None, :]
+    g0eff_r = np.linalg.inv(np.linalg.inv(g_r) + sig * w[None, :])
+    w1 = 0.3
+    rem = []
+    for u in (0.02, 0.01):
+        got = impurity.update(gl, sig, w, 0.0, u, w1) * w[None, :]
+        pred = u * (w1 - 0.5) * s + u * u * w1 * (1 - w1) * (s @ g0eff_r @ s)
+        rem.append(np.max(np.abs(got - pred)))
+    assert rem[0] / rem[1] > 6.0, rem
