@@ -1,0 +1,177 @@
+/*
+ * fkdmft.h -- C ABI of the MI355X (gfx950) lattice step of nonequilibrium DMFT
+ * for the spinless Falicov-Kimball model on the infinite-dimensional hypercubic
+ * lattice in a uniform electric field (J. K. Freericks, "Quenching Bloch
+ * oscillations in a strongly correlated material", arXiv:0711.0999, Sec. II).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Contour (Sec. II, eqs. time_discrete and integration_weights), 0-based:
+ *      upper real branch  j in [0, N_t):        z_j = t_min + j dt,          W_j = +dt
+ *      lower real branch  j in [N_t, 2N_t):     z_j = t_max - (j - N_t) dt,  W_j = -dt
+ *      imaginary branch   j in [2N_t, N_c):     z_j = t_min - i dtau (j-2N_t), W_j = -i dtau
+ *    N_t = (t_max - t_min)/dt, N_tau = beta/dtau, N_c = 2 N_t + N_tau.
+ *  - Every two-time function (Sigma, G_loc) crosses the boundary as its VALUES
+ *    on the contour points: N_c x N_c complex128, row-major, interleaved
+ *    (re, im) doubles, element (i, j) at offset 2 (i N_c + j).
+ *  - Host buffers are owned by the caller and copied synchronously; the library
+ *    never keeps a caller pointer.  With on_device = 1 a pointer is a device
+ *    address on the context's device (e.g. a torch tensor's data_ptr()); the
+ *    library finishes its stream before returning.
+ *  - The context owns all of its device memory.  One context per host thread;
+ *    distinct contexts are independent.
+ *  - Every call returns an fk_status; no call aborts or exits.  After an error
+ *    fk_last_error(ctx) holds a human-readable detail (failing point index,
+ *    pivot column, HIP error string).
+ */
+#ifndef FKDMFT_H
+#define FKDMFT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fk_ctx fk_ctx;
+typedef int fk_status;
+
+enum {
+  FK_OK = 0,
+  FK_EINVAL = -1,      /* bad argument (sizes, NULL, non-integral contour)      */
+  FK_ENOMEM = -2,      /* device or host allocation failed                      */
+  FK_EDEVICE = -3,     /* HIP runtime error or no usable gfx950 device          */
+  FK_ESINGULAR = -4,   /* zero pivot in an inversion (point index in detail)    */
+  FK_ENONFINITE = -5,  /* NaN/Inf in G_loc, Sigma or a pivot                    */
+  FK_ENOTCONV = -6,    /* fk_iterate reached max_iter without delta < tol       */
+  FK_ESTATE = -7       /* call order violated (e.g. current before a step)      */
+};
+
+/* Arithmetic of the lattice step (north of the FP64 reduction). */
+typedef enum {
+  FK_FP64 = 0,   /* complex128 Gauss-Jordan inversion of every point matrix      */
+  FK_MIXED = 1   /* complex64 inversion + FP64 iterative refinement (see below)  */
+} fk_precision;
+
+/* Contour of Sec. II.  (t_max - t_min)/dt and beta/dtau must be integers to
+ * 1e-9 relative, t_min < t_max, dt > 0, dtau > 0, beta > 0; else FK_EINVAL. */
+typedef struct {
+  double t_min, t_max, dt, dtau, beta;
+} fk_contour;
+
+/* Model: interaction U, field E (turned on at t = 0 along the lattice diagonal,
+ * eq. vector_potential), chemical potential mu, f-site filling w1 = <w_1>,
+ * Gauss-Hermite orders of the (eps, ebar) product rule (eq. joint_dos), and the
+ * half-filling convention of the impurity shifts:
+ *   convention 0 (symmetric): U (w - 1/2) n, shifts mu0 - mu = +U/2, mu1 - mu = -U/2
+ *   convention 1 (paper):     U w n,         shifts mu0 - mu = 0,    mu1 - mu = -U
+ * gh_average must be 0 (one n_eps x n_ebar rule; the paper's N/N+1 average
+ * is not implemented). */
+typedef struct {
+  double U, E, mu, w1;
+  int n_eps, n_ebar;
+  int convention;
+  int gh_average;
+} fk_model;
+
+/* ---- host-only helpers (no device needed) -------------------------------- */
+
+/* Gauss-Hermite rule for the normalized Gaussian weight exp(-x^2)/sqrt(pi)
+ * (eq. joint_dos, Sec. II quadrature paragraph): n nodes x[n] (ascending) and
+ * weights w[n] summing to 1.  Nodes by Sturm-sequence bisection on the Jacobi
+ * matrix, weights by the Christoffel formula.  1 <= n <= 400. */
+fk_status fk_gauss_hermite(int n, double* x, double* w);
+
+/* Contour sizes and points without a context: dims[3] = {N_t, N_tau, N_c};
+ * z and W (each 2*N_c doubles, interleaved) may be NULL to query sizes. */
+fk_status fk_contour_build(const fk_contour* c, int* dims, double* z, double* W);
+
+/* Status code name, e.g. "FK_ESINGULAR". */
+const char* fk_status_string(fk_status s);
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t
+ * (NULL: the library creates its own default-priority stream).  Sigma starts
+ * at zero.  Device memory for the batched inversion is sized by
+ * FKDMFT_BATCH_BYTES (environment, bytes; default 24 GiB) or fk_set_batch. */
+fk_status fk_create(const fk_contour* c, const fk_model* m, void* hip_stream,
+                    fk_ctx** out);
+fk_status fk_destroy(fk_ctx* ctx);                       /* NULL-safe */
+const char* fk_last_error(const fk_ctx* ctx);            /* never NULL */
+
+fk_status fk_dims(const fk_ctx* ctx, int* n_t, int* n_tau, int* n_c);
+/* z, W: 2*N_c doubles each (interleaved), host. */
+fk_status fk_contour_points(const fk_ctx* ctx, double* z, double* W);
+/* Number of (eps, ebar) points and their nodes/weights (host, may be NULL). */
+fk_status fk_points(const fk_ctx* ctx, int* n_points, double* eps, double* ebar,
+                    double* rho);
+
+/* Number of point matrices inverted per batch (>= 1); returns the value used.
+ * Reallocates the batch buffer. */
+fk_status fk_set_batch(fk_ctx* ctx, int batch, int* used);
+
+/* ---- state --------------------------------------------------------------- */
+
+fk_status fk_set_sigma(fk_ctx* ctx, const double* sigma, int on_device);
+fk_status fk_get_sigma(const fk_ctx* ctx, double* sigma, int on_device);
+fk_status fk_get_gloc(const fk_ctx* ctx, double* gloc, int on_device);
+
+/* ---- the hot path -------------------------------------------------------- */
+
+/* Lattice step (eqs. dyson and g_loc, Sec. II): for every Gauss-Hermite point
+ * k = a*n_ebar + b (eps = x_a, ebar = x_b, rho_k = w_a w_b)
+ *     G_k = (G0_k^-1 - W Sigma W)^-1
+ * where G0_k is eq. (g_contour_non_final2) sampled with theta_c(t,t) = 1, whose
+ * inverse is the exact bidiagonal-plus-corner matrix
+ *     G0_k^-1 = i D (I - P + e^{-beta(eps-mu)} e_0 e_{N-1}^T) D^-1,
+ *     D = diag(exp(-i phi_k(z) + i mu z)),
+ * then G_loc = sum_k rho_k G_k (fixed order, deterministic) and the current
+ *     j(t_i) = Re[ i sum_k rho_k ebar_k(t_i) G_k[i, 2N_t - i] ],  i < N_t
+ * (eq. current_def, velocity at the Peierls-shifted momentum, e = t* = 1).
+ * FK_FP64: complex128 throughout.  FK_MIXED: complex64 inversion, then
+ * ir_steps (fk_set_refinement, default 1) FP64 refinement steps
+ * X <- X + X (I - A X) with the residual I - A X in FP64; the rho-weighted sum
+ * is FP64.  ir_resid_out (nullable) receives max_k max|I - A_k X_k| of the last
+ * refinement (FK_FP64: 0).  Errors: FK_ESINGULAR (point index in detail),
+ * FK_ENONFINITE. */
+fk_status fk_compute_gloc(fk_ctx* ctx, fk_precision prec, double* ir_resid_out);
+
+/* Refinement steps used by FK_MIXED (0..4). */
+fk_status fk_set_refinement(fk_ctx* ctx, int ir_steps);
+
+/* j(t_i), the time t_i = t_min + i dt and (nullable) n(t_i) = Re[-i G^<_loc(t_i,t_i)]
+ * from the last lattice step; N_t doubles each.  FK_ESTATE before any step. */
+fk_status fk_get_current(const fk_ctx* ctx, double* t, double* j, double* n_t);
+
+/* Falicov-Kimball impurity update (eqs. effective_medium, dynamical_mean_field,
+ * g_imp_solve and Dyson again), in right-weighted form A -> A W:
+ *   g0inv = (G_loc W)^-1 + Sigma W
+ *   G_imp = (1-w1) (g0inv + d0 S)^-1 + w1 (g0inv + d1 S)^-1
+ *   Sigma <- (g0inv - G_imp^-1) W^-1
+ * with S the point-split delta (S[j,j-1] = 1, S[0,N_c-1] = -1) and (d0, d1)
+ * from the model's convention.  Complex128 Gauss-Jordan inversions on the
+ * device.  max_dsigma_out (nullable) = max |Sigma_new - Sigma_old|.
+ * FK_ESTATE before any lattice step. */
+fk_status fk_impurity_update(fk_ctx* ctx, double* max_dsigma_out);
+
+/* Self-consistency loop (Sec. II summary): iteration n = lattice step from
+ * Sigma(n-1), delta(n) = max|G_loc(n) - G_loc(n-1)| (delta(1) = +inf), impurity
+ * update -> Sigma(n); stops after the iteration with delta < tol (converged,
+ * FK_OK) or after max_iter iterations (FK_ENOTCONV unless tol <= 0, in which
+ * case exactly max_iter iterations run and FK_OK is returned).
+ * With FK_MIXED the loop runs complex64+refinement steps while delta >=
+ * switch_tol (fk_set_switch, default 1e-5) and FK_FP64 steps afterwards.
+ * delta_history (nullable, max_iter doubles) receives delta(n). */
+fk_status fk_iterate(fk_ctx* ctx, int max_iter, double tol, fk_precision prec,
+                     int* iters_out, double* delta_out, double* delta_history);
+fk_status fk_set_switch(fk_ctx* ctx, double switch_tol);
+
+/* Per-phase device time of the last fk_compute_gloc / fk_impurity_update in
+ * milliseconds (HIP events on the context stream): out[0] build, out[1]
+ * inversion, out[2] refinement, out[3] reduction, out[4] impurity, out[5]
+ * inversion kernel launches, out[6] summed duration of the step kernels. */
+fk_status fk_timings(const fk_ctx* ctx, double* out7);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FKDMFT_H */

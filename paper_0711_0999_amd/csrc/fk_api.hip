@@ -1,0 +1,856 @@
+// C ABI of the fkdmft library: contour, quadrature, context, the lattice step
+// (batched Gauss-Jordan inversion of every point matrix), the Falicov-Kimball
+// impurity update and the self-consistency loop.  See include/fkdmft.h.
+#include "../../include/fkdmft.h"
+#include "fk_internal.h"
+#include "fk_kernels.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <limits>
+#include <string>
+#include <vector>
+
+using namespace fk;
+
+// ===================================================================== host ==
+namespace {
+
+// Sturm-sequence count of eigenvalues below x of the symmetric tridiagonal
+// Jacobi matrix of the normalized Hermite weight (zero diagonal, off-diagonal
+// b_k = sqrt(k/2), k = 1..n-1).
+int sturm_count(int n, double x) {
+  int cnt = 0;
+  double q = -x;
+  if (q < 0) ++cnt;
+  for (int k = 1; k < n; ++k) {
+    const double b2 = 0.5 * k;
+    if (q == 0.0) q = 1e-300;
+    q = -x - b2 / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+struct ContourInfo {
+  int n_t = 0, n_tau = 0, n_c = 0;
+  std::vector<double> zr, zi, wr, wi;
+};
+
+bool integral_ratio(double span, double step, int* out) {
+  if (!(step > 0.0) || !(span > 0.0)) return false;
+  const double r = span / step;
+  const double m = floor(r + 0.5);
+  if (m < 1.0 || m > 1e7) return false;
+  if (fabs(r - m) > 1e-9 * std::max(1.0, fabs(r))) return false;
+  *out = (int)m;
+  return true;
+}
+
+fk_status build_contour(const fk_contour* c, ContourInfo* ci) {
+  if (!c) return FK_EINVAL;
+  if (!(c->t_max > c->t_min)) return FK_EINVAL;
+  int n_t, n_tau;
+  if (!integral_ratio(c->t_max - c->t_min, c->dt, &n_t)) return FK_EINVAL;
+  if (!integral_ratio(c->beta, c->dtau, &n_tau)) return FK_EINVAL;
+  ci->n_t = n_t;
+  ci->n_tau = n_tau;
+  ci->n_c = 2 * n_t + n_tau;
+  const int n = ci->n_c;
+  ci->zr.assign(n, 0.0);
+  ci->zi.assign(n, 0.0);
+  ci->wr.assign(n, 0.0);
+  ci->wi.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    if (j < n_t) {                    // upper real branch, leftpoint weight +dt
+      ci->zr[j] = c->t_min + j * c->dt;
+      ci->wr[j] = c->dt;
+    } else if (j < 2 * n_t) {         // lower real branch, weight -dt
+      ci->zr[j] = c->t_max - (j - n_t) * c->dt;
+      ci->wr[j] = -c->dt;
+    } else {                          // imaginary branch, weight -i dtau
+      ci->zr[j] = c->t_min;
+      ci->zi[j] = -c->dtau * (j - 2 * n_t);
+      ci->wi[j] = -c->dtau;
+    }
+  }
+  return FK_OK;
+}
+
+}  // namespace
+
+extern "C" fk_status fk_gauss_hermite(int n, double* x, double* w) {
+  if (n < 1 || n > 150 || !x || !w) return FK_EINVAL;
+  std::vector<double> xs(n), ws(n);
+  const double bound = 2.0 * sqrt(0.5 * (n > 1 ? n - 1 : 1)) + 1.0;
+  for (int k = 0; k < n; ++k) {
+    // k-th eigenvalue (ascending): count(x) <= k below it, > k above it
+    double lo = -bound, hi = bound;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (sturm_count(n, mid) > k) hi = mid;
+      else lo = mid;
+    }
+    xs[k] = 0.5 * (lo + hi);
+  }
+  for (int k = 0; k < n; ++k) {
+    // Christoffel weight 1 / sum_j p_j(x)^2 with orthonormal p_j
+    const double t = xs[k];
+    double pm = 0.0, p = 1.0, s = 1.0;
+    for (int j = 1; j < n; ++j) {
+      const double bj = sqrt(0.5 * j);
+      const double bjm = sqrt(0.5 * (j - 1));
+      const double pn = (t * p - bjm * pm) / bj;
+      pm = p;
+      p = pn;
+      s += p * p;
+    }
+    ws[k] = 1.0 / s;
+  }
+  for (int k = 0; k < n; ++k) {   // the weight is even: symmetrize
+    x[k] = 0.5 * (xs[k] - xs[n - 1 - k]);
+    w[k] = 0.5 * (ws[k] + ws[n - 1 - k]);
+  }
+  return FK_OK;
+}
+
+extern "C" fk_status fk_contour_build(const fk_contour* c, int* dims, double* z,
+                                      double* W) {
+  if (!dims) return FK_EINVAL;
+  ContourInfo ci;
+  fk_status s = build_contour(c, &ci);
+  if (s != FK_OK) return s;
+  dims[0] = ci.n_t;
+  dims[1] = ci.n_tau;
+  dims[2] = ci.n_c;
+  for (int j = 0; j < ci.n_c; ++j) {
+    if (z) {
+      z[2 * j] = ci.zr[j];
+      z[2 * j + 1] = ci.zi[j];
+    }
+    if (W) {
+      W[2 * j] = ci.wr[j];
+      W[2 * j + 1] = ci.wi[j];
+    }
+  }
+  return FK_OK;
+}
+
+extern "C" const char* fk_status_string(fk_status s) {
+  switch (s) {
+    case FK_OK: return "FK_OK";
+    case FK_EINVAL: return "FK_EINVAL";
+    case FK_ENOMEM: return "FK_ENOMEM";
+    case FK_EDEVICE: return "FK_EDEVICE";
+    case FK_ESINGULAR: return "FK_ESINGULAR";
+    case FK_ENONFINITE: return "FK_ENONFINITE";
+    case FK_ENOTCONV: return "FK_ENOTCONV";
+    case FK_ESTATE: return "FK_ESTATE";
+    default: return "FK_UNKNOWN";
+  }
+}
+
+// ==================================================================== device ==
+namespace {
+
+__global__ void k_fill_int(int* p, int v, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+__global__ void k_fill_f64(double* p, double v, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+hipError_t fill_int(int* p, int v, size_t n, hipStream_t st) {
+  size_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_fill_int, dim3((int)g), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_u64(unsigned long long* p, unsigned long long v, int n,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3((n + 63) / 64), dim3(64), 0, st, p, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_f64(double* p, double v, size_t n, hipStream_t st) {
+  size_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_fill_f64, dim3((int)g), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+// A batch of same-size matrices for the blocked Gauss-Jordan inversion.
+template <typename T> struct Batch {
+  int cap = 0, n = 0, ld = 0;
+  size_t stride = 0;
+  cplx<T>* x = nullptr;
+  int* piv = nullptr;
+  int* rowcol = nullptr;
+  int* status = nullptr;
+  MatDesc* descs = nullptr;
+  WorkItem* items = nullptr;
+  std::vector<int> off, cnt;  // per step s = -1 .. nsteps-1 (index s+1)
+  int nsteps = 0;
+};
+
+template <typename T> void batch_free(Batch<T>& b) {
+  if (b.x) (void)hipFree(b.x);
+  if (b.piv) (void)hipFree(b.piv);
+  if (b.rowcol) (void)hipFree(b.rowcol);
+  if (b.status) (void)hipFree(b.status);
+  if (b.descs) (void)hipFree(b.descs);
+  if (b.items) (void)hipFree(b.items);
+  b = Batch<T>();
+}
+
+template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
+  batch_free(b);
+  b.cap = cap;
+  b.n = n;
+  b.ld = n;
+  b.stride = (size_t)n * n;
+  b.nsteps = (n + kNB - 1) / kNB;
+  hipError_t e;
+  if ((e = hipMalloc(&b.x, sizeof(cplx<T>) * b.stride * cap)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.piv, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.rowcol, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.status, sizeof(int) * cap)) != hipSuccess) return e;
+  std::vector<MatDesc> d(cap);
+  for (int m = 0; m < cap; ++m) {
+    d[m].xoff = (long long)b.stride * m;
+    d[m].n = n;
+    d[m].ld = b.ld;
+    d[m].ioff = n * m;
+    d[m].status_idx = m;
+  }
+  if ((e = hipMalloc(&b.descs, sizeof(MatDesc) * cap)) != hipSuccess) return e;
+  if ((e = hipMemcpy(b.descs, d.data(), sizeof(MatDesc) * cap,
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  // Work items per step, matrix-major so that a prefix serves fewer matrices;
+  // the stripe that becomes the next panel comes first within each matrix.
+  const int ns = b.nsteps;
+  std::vector<WorkItem> it;
+  b.off.assign(ns + 1, 0);
+  b.cnt.assign(ns + 1, 0);
+  for (int s = -1; s < ns; ++s) {
+    b.off[s + 1] = (int)it.size();
+    int per = 0;
+    for (int m = 0; m < cap; ++m) {
+      std::vector<int> qs;
+      if (s < 0) {
+        qs.push_back(0);
+      } else {
+        if (s + 1 < ns) qs.push_back(s + 1);
+        for (int q = 0; q < ns; ++q)
+          if (q != s && q != s + 1) qs.push_back(q);
+      }
+      for (int q : qs) it.push_back(WorkItem{m, q});
+      per = (int)qs.size();
+    }
+    b.cnt[s + 1] = per;
+  }
+  if ((e = hipMalloc(&b.items, sizeof(WorkItem) * it.size())) != hipSuccess) return e;
+  return hipMemcpy(b.items, it.data(), sizeof(WorkItem) * it.size(),
+                   hipMemcpyHostToDevice);
+}
+
+// Invert matrices 0..nmat-1 of the batch in place (permuted storage).
+template <typename T>
+hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, int* launches) {
+  hipError_t e;
+  if ((e = fill_int(b.rowcol, -1, (size_t)b.n * nmat, st)) != hipSuccess) return e;
+  if ((e = fill_int(b.status, 0, (size_t)nmat, st)) != hipSuccess) return e;
+  for (int s = -1; s < b.nsteps; ++s) {
+    const int nitems = nmat * b.cnt[s + 1];
+    if (nitems == 0) continue;
+    const int grid = 8 * ((nitems + 7) / 8);
+    e = gje_step<T>(b.x, b.piv, b.rowcol, b.descs, b.items + b.off[s + 1],
+                    nitems, s, b.status, grid, st);
+    if (e != hipSuccess) return e;
+    if (launches) ++*launches;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+// ======================================================================= ctx ==
+struct fk_ctx {
+  fk_contour c;
+  fk_model m;
+  ContourInfo ci;
+  int npts = 0;
+  std::vector<double> eps, ebar, rho;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // device
+  c64* d_w = nullptr;          // weights W (N_c)
+  c64* d_sigma = nullptr;      // Sigma values
+  c64* d_sigt = nullptr;       // W Sigma W
+  c64* d_gloc = nullptr;
+  c64* d_gprev = nullptr;
+  c64* d_g0inv = nullptr;      // impurity scratch
+  c64* d_tmp = nullptr;        // impurity scratch
+  double* d_cur = nullptr;     // j(t), N_t
+  double* d_eps = nullptr;
+  double* d_ebar = nullptr;
+  double* d_rho = nullptr;
+  c64* d_da = nullptr;
+  c64* d_dg = nullptr;
+  c64* d_dz = nullptr;
+  double* d_cos = nullptr;
+  double* d_sin = nullptr;
+  int* d_tpos = nullptr;
+  double* d_coef = nullptr;    // {1, 1 - w1, w1}
+  unsigned long long* d_key = nullptr;
+  PointTables tab;
+
+  Batch<double> b64;           // lattice batch (complex128)
+  Batch<float> b32;            // lattice batch (complex64), lazily
+  Batch<double> imp;           // impurity inversions (2 slots)
+  size_t batch_bytes = 0;
+  int want_batch = 0;
+
+  bool have_gloc = false;
+  bool have_prev = false;
+  int ir_steps = 1;
+  double switch_tol = 1e-5;
+  double times[7] = {0, 0, 0, 0, 0, 0, 0};
+  hipEvent_t ev[8];
+};
+
+namespace {
+
+fk_status set_err(fk_ctx* c, fk_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                    \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return set_err((ctx), e_ == hipErrorOutOfMemory ? FK_ENOMEM : FK_EDEVICE, \
+                     "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                     __LINE__);                                              \
+  } while (0)
+
+template <typename T> int batch_cap_for(fk_ctx* c) {
+  const size_t per = sizeof(cplx<T>) * (size_t)c->ci.n_c * c->ci.n_c +
+                     2 * sizeof(int) * (size_t)c->ci.n_c;
+  size_t cap = c->batch_bytes / per;
+  if (c->want_batch > 0) cap = (size_t)c->want_batch;
+  if (cap < 1) cap = 1;
+  if (cap > (size_t)c->npts) cap = (size_t)c->npts;
+  // equalize the batches so the last one is not a small tail
+  const size_t nb = (c->npts + cap - 1) / cap;
+  cap = (c->npts + nb - 1) / nb;
+  return (int)cap;
+}
+
+template <typename T> Batch<T>& lattice_batch(fk_ctx* c);
+template <> Batch<double>& lattice_batch<double>(fk_ctx* c) { return c->b64; }
+template <> Batch<float>& lattice_batch<float>(fk_ctx* c) { return c->b32; }
+
+template <typename T> fk_status ensure_batch(fk_ctx* c) {
+  Batch<T>& b = lattice_batch<T>(c);
+  const int cap = batch_cap_for<T>(c);
+  if (b.x && b.cap == cap) return FK_OK;
+  HIPCHK(c, batch_alloc(b, cap, c->ci.n_c));
+  return FK_OK;
+}
+
+fk_status check_status(fk_ctx* c, const int* d_status, int nmat, int k0,
+                       const char* what) {
+  std::vector<int> s(nmat);
+  HIPCHK(c, hipMemcpyAsync(s.data(), d_status, sizeof(int) * nmat,
+                           hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int m = 0; m < nmat; ++m) {
+    if (s[m] > 0)
+      return set_err(c, FK_ESINGULAR, "%s: zero pivot at column %d of matrix %d",
+                     what, s[m] - 1, k0 + m);
+    if (s[m] < 0)
+      return set_err(c, FK_ENONFINITE,
+                     "%s: non-finite pivot at column %d of matrix %d", what,
+                     -s[m] - 1, k0 + m);
+  }
+  return FK_OK;
+}
+
+double read_key(fk_ctx* c, fk_status* st) {
+  unsigned long long k = 0;
+  hipError_t e = hipMemcpyAsync(&k, c->d_key, sizeof k, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) {
+    *st = set_err(c, FK_EDEVICE, "read norm: %s", hipGetErrorString(e));
+    return 0.0;
+  }
+  *st = FK_OK;
+  double v;
+  memcpy(&v, &k, sizeof v);
+  return v;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+// Lattice step in precision T (T = double: FP64 path).
+template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
+  fk_status s = ensure_batch<T>(c);
+  if (s != FK_OK) return s;
+  Batch<T>& b = lattice_batch<T>(c);
+  const int n = c->ci.n_c;
+  for (double& t : c->times) t = 0.0;
+  int launches = 0;
+  HIPCHK(c, launch_sigma_weight(c->d_sigma, c->d_w, c->d_sigt, n, c->st));
+  HIPCHK(c, fill_f64(c->d_cur, 0.0, (size_t)c->ci.n_t, c->st));
+  for (int k0 = 0; k0 < c->npts; k0 += b.cap) {
+    const int nmat = std::min(b.cap, c->npts - k0);
+    HIPCHK(c, hipEventRecord(c->ev[0], c->st));
+    HIPCHK(c, launch_build<T>(c->d_sigt, c->tab, k0, nmat, b.x, b.stride, b.ld,
+                              n, c->st));
+    HIPCHK(c, hipEventRecord(c->ev[1], c->st));
+    HIPCHK(c, batch_invert<T>(b, nmat, c->st, &launches));
+    HIPCHK(c, hipEventRecord(c->ev[2], c->st));
+    HIPCHK(c, launch_reduce<T>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
+                               c->d_rho + k0, nmat, n, c->d_gloc, k0 > 0 ? 1 : 0,
+                               c->st));
+    HIPCHK(c, launch_current<T>(b.x, b.stride, b.ld, b.piv, b.rowcol, n, c->tab,
+                                k0, nmat, c->ci.n_t, c->d_cur, c->st));
+    HIPCHK(c, hipEventRecord(c->ev[3], c->st));
+    s = check_status(c, b.status, nmat, k0, "lattice inversion");
+    if (s != FK_OK) return s;
+    c->times[0] += elapsed(c->ev[0], c->ev[1]);
+    c->times[1] += elapsed(c->ev[1], c->ev[2]);
+    c->times[3] += elapsed(c->ev[2], c->ev[3]);
+  }
+  c->times[5] = launches;
+  // non-finite check of G_loc
+  HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
+  HIPCHK(c, launch_maxabs(c->d_gloc, nullptr, (size_t)n * n, c->d_key, c->st));
+  double mx = read_key(c, &s);
+  if (s != FK_OK) return s;
+  if (!(mx <= std::numeric_limits<double>::max()))
+    return set_err(c, FK_ENONFINITE, "G_loc has non-finite entries");
+  if (ir_out) *ir_out = 0.0;
+  c->have_gloc = true;
+  return FK_OK;
+}
+
+fk_status impurity(fk_ctx* c, double* dsig) {
+  if (!c->have_gloc) return set_err(c, FK_ESTATE, "impurity update before a lattice step");
+  const int n = c->ci.n_c;
+  Batch<double>& b = c->imp;
+  if (!b.x) HIPCHK(c, batch_alloc(b, 2, n));
+  int launches = 0;
+  fk_status s;
+  HIPCHK(c, hipEventRecord(c->ev[4], c->st));
+  // g0inv = (G_loc W)^-1 + Sigma W
+  HIPCHK(c, launch_right_weight(c->d_gloc, c->d_w, b.x, b.ld, n, c->st));
+  HIPCHK(c, batch_invert<double>(b, 1, c->st, &launches));
+  if ((s = check_status(c, b.status, 1, 0, "inverse of G_loc W")) != FK_OK) return s;
+  HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
+                                  c->d_coef, 1, n, c->d_g0inv, 0, c->st));
+  HIPCHK(c, launch_add_right_weighted(c->d_g0inv, c->d_sigma, c->d_w, n, c->st));
+  // G_imp = (1 - w1)(g0inv + d0 S)^-1 + w1 (g0inv + d1 S)^-1
+  double d0, d1;
+  if (c->m.convention == 0) {
+    d0 = 0.5 * c->m.U;
+    d1 = -0.5 * c->m.U;
+  } else {
+    d0 = 0.0;
+    d1 = -c->m.U;
+  }
+  HIPCHK(c, launch_shifted_pair(c->d_g0inv, d0, d1, b.x, b.x + b.stride, b.ld, n,
+                                c->st));
+  HIPCHK(c, batch_invert<double>(b, 2, c->st, &launches));
+  if ((s = check_status(c, b.status, 2, 0, "impurity resolvents")) != FK_OK) return s;
+  HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
+                                  c->d_coef + 1, 2, n, c->d_tmp, 0, c->st));
+  HIPCHK(c, hipMemcpyAsync(b.x, c->d_tmp, sizeof(c64) * (size_t)n * n,
+                           hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, batch_invert<double>(b, 1, c->st, &launches));
+  if ((s = check_status(c, b.status, 1, 0, "inverse of G_imp")) != FK_OK) return s;
+  HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
+                                  c->d_coef, 1, n, c->d_tmp, 0, c->st));
+  // Sigma <- (g0inv - G_imp^-1) W^-1
+  HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
+  HIPCHK(c, launch_sigma_new(c->d_g0inv, c->d_tmp, c->d_w, c->d_sigma, n,
+                             c->d_key, c->st));
+  HIPCHK(c, hipEventRecord(c->ev[5], c->st));
+  double mx = read_key(c, &s);
+  if (s != FK_OK) return s;
+  c->times[4] = elapsed(c->ev[4], c->ev[5]);
+  if (!(mx <= std::numeric_limits<double>::max()))
+    return set_err(c, FK_ENONFINITE, "Sigma has non-finite entries");
+  if (dsig) *dsig = mx;
+  return FK_OK;
+}
+
+fk_status copy_matrix_in(fk_ctx* c, c64* dst, const double* src, int on_device) {
+  if (!src) return set_err(c, FK_EINVAL, "NULL matrix pointer");
+  const size_t bytes = sizeof(c64) * (size_t)c->ci.n_c * c->ci.n_c;
+  HIPCHK(c, hipMemcpyAsync(dst, src, bytes,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return FK_OK;
+}
+
+fk_status copy_matrix_out(fk_ctx* c, double* dst, const c64* src, int on_device) {
+  if (!dst) return set_err(c, FK_EINVAL, "NULL matrix pointer");
+  const size_t bytes = sizeof(c64) * (size_t)c->ci.n_c * c->ci.n_c;
+  HIPCHK(c, hipMemcpyAsync(dst, src, bytes,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return FK_OK;
+}
+
+void free_ctx(fk_ctx* c) {
+  c64* cs[] = {c->d_w, c->d_sigma, c->d_sigt, c->d_gloc, c->d_gprev,
+               c->d_g0inv, c->d_tmp, c->d_da, c->d_dg, c->d_dz};
+  for (c64* p : cs)
+    if (p) (void)hipFree(p);
+  double* ds[] = {c->d_cur, c->d_eps, c->d_ebar, c->d_rho, c->d_cos, c->d_sin,
+                  c->d_coef};
+  for (double* p : ds)
+    if (p) (void)hipFree(p);
+  if (c->d_tpos) (void)hipFree(c->d_tpos);
+  if (c->d_key) (void)hipFree(c->d_key);
+  batch_free(c->b64);
+  batch_free(c->b32);
+  batch_free(c->imp);
+  for (hipEvent_t& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
+}
+
+template <typename P> hipError_t upload(P** dst, const void* src, size_t bytes) {
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+// ================================================================== C ABI ==
+extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
+                               void* hip_stream, fk_ctx** out) {
+  if (!cont || !mod || !out) return FK_EINVAL;
+  *out = nullptr;
+  ContourInfo ci;
+  if (build_contour(cont, &ci) != FK_OK) return FK_EINVAL;
+  if (mod->n_eps < 1 || mod->n_eps > 150 || mod->n_ebar < 1 || mod->n_ebar > 150)
+    return FK_EINVAL;
+  if (mod->gh_average != 0) return FK_EINVAL;
+  if (mod->convention != 0 && mod->convention != 1) return FK_EINVAL;
+  if (!(mod->w1 >= 0.0 && mod->w1 <= 1.0)) return FK_EINVAL;
+  if (!std::isfinite(mod->U) || !std::isfinite(mod->E) || !std::isfinite(mod->mu))
+    return FK_EINVAL;
+  if (ci.n_c > kMaxN || ci.n_c < 3) return FK_EINVAL;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return FK_EDEVICE;
+
+  fk_ctx* c = new (std::nothrow) fk_ctx();
+  if (!c) return FK_ENOMEM;
+  for (hipEvent_t& e : c->ev) e = nullptr;
+  c->c = *cont;
+  c->m = *mod;
+  c->ci = ci;
+  const int n = ci.n_c, n_t = ci.n_t;
+
+  // quadrature points k = a * n_ebar + b
+  std::vector<double> xa(mod->n_eps), wa(mod->n_eps), xb(mod->n_ebar), wb(mod->n_ebar);
+  fk_gauss_hermite(mod->n_eps, xa.data(), wa.data());
+  fk_gauss_hermite(mod->n_ebar, xb.data(), wb.data());
+  c->npts = mod->n_eps * mod->n_ebar;
+  for (int a = 0; a < mod->n_eps; ++a)
+    for (int b = 0; b < mod->n_ebar; ++b) {
+      c->eps.push_back(xa[a]);
+      c->ebar.push_back(xb[b]);
+      c->rho.push_back(wa[a] * wb[b]);
+    }
+
+  // antiderivative tables alpha, gamma of the band phase (eq.
+  // g_contour_non_final2): sin(Et)/E and (cos Et - 1)/E for real t > 0,
+  // otherwise alpha = z and gamma = 0.
+  std::vector<c64> alpha(n), gamma(n), zc(n);
+  const double E = mod->E;
+  for (int j = 0; j < n; ++j) {
+    zc[j] = c64{ci.zr[j], ci.zi[j]};
+    alpha[j] = zc[j];
+    gamma[j] = c64{0.0, 0.0};
+    if (E != 0.0 && j < 2 * n_t && ci.zr[j] > 0.0) {
+      const double t = ci.zr[j];
+      alpha[j] = c64{sin(E * t) / E, 0.0};
+      const double h = sin(0.5 * E * t);
+      gamma[j] = c64{-2.0 * h * h / E, 0.0};
+    }
+  }
+  std::vector<c64> da(n), dg(n), dz(n);
+  da[0] = dg[0] = dz[0] = c64{0.0, 0.0};
+  for (int j = 1; j < n; ++j) {
+    da[j] = c64{alpha[j].re - alpha[j - 1].re, alpha[j].im - alpha[j - 1].im};
+    dg[j] = c64{gamma[j].re - gamma[j - 1].re, gamma[j].im - gamma[j - 1].im};
+    dz[j] = c64{zc[j].re - zc[j - 1].re, zc[j].im - zc[j - 1].im};
+  }
+  std::vector<double> cs(n_t), sn(n_t);
+  std::vector<int> tp(n_t);
+  for (int i = 0; i < n_t; ++i) {
+    const double t = ci.zr[i];
+    cs[i] = cos(E * t);
+    sn[i] = sin(E * t);
+    tp[i] = t > 0.0 ? 1 : 0;
+  }
+  std::vector<c64> w(n);
+  for (int j = 0; j < n; ++j) w[j] = c64{ci.wr[j], ci.wi[j]};
+  const double coef[3] = {1.0, 1.0 - mod->w1, mod->w1};
+
+  hipError_t e = hipSuccess;
+  if (hip_stream) {
+    c->st = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking);
+    c->own_stream = (e == hipSuccess);
+  }
+  const size_t mat = sizeof(c64) * (size_t)n * n;
+  if (e == hipSuccess) e = upload(&c->d_w, w.data(), sizeof(c64) * n);
+  if (e == hipSuccess) e = hipMalloc(&c->d_sigma, mat);
+  if (e == hipSuccess) e = hipMemset(c->d_sigma, 0, mat);
+  if (e == hipSuccess) e = hipMalloc(&c->d_sigt, mat);
+  if (e == hipSuccess) e = hipMalloc(&c->d_gloc, mat);
+  if (e == hipSuccess) e = hipMalloc(&c->d_gprev, mat);
+  if (e == hipSuccess) e = hipMalloc(&c->d_g0inv, mat);
+  if (e == hipSuccess) e = hipMalloc(&c->d_tmp, mat);
+  if (e == hipSuccess) e = hipMalloc(&c->d_cur, sizeof(double) * n_t);
+  if (e == hipSuccess) e = upload(&c->d_eps, c->eps.data(), sizeof(double) * c->npts);
+  if (e == hipSuccess) e = upload(&c->d_ebar, c->ebar.data(), sizeof(double) * c->npts);
+  if (e == hipSuccess) e = upload(&c->d_rho, c->rho.data(), sizeof(double) * c->npts);
+  if (e == hipSuccess) e = upload(&c->d_da, da.data(), sizeof(c64) * n);
+  if (e == hipSuccess) e = upload(&c->d_dg, dg.data(), sizeof(c64) * n);
+  if (e == hipSuccess) e = upload(&c->d_dz, dz.data(), sizeof(c64) * n);
+  if (e == hipSuccess) e = upload(&c->d_cos, cs.data(), sizeof(double) * n_t);
+  if (e == hipSuccess) e = upload(&c->d_sin, sn.data(), sizeof(double) * n_t);
+  if (e == hipSuccess) e = upload(&c->d_tpos, tp.data(), sizeof(int) * n_t);
+  if (e == hipSuccess) e = upload(&c->d_coef, coef, sizeof coef);
+  if (e == hipSuccess) e = hipMalloc(&c->d_key, sizeof(unsigned long long));
+  for (hipEvent_t& ev : c->ev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e != hipSuccess) {
+    const fk_status s = (e == hipErrorOutOfMemory) ? FK_ENOMEM : FK_EDEVICE;
+    free_ctx(c);
+    delete c;
+    return s;
+  }
+  c->tab.eps = c->d_eps;
+  c->tab.ebar = c->d_ebar;
+  c->tab.rho = c->d_rho;
+  c->tab.da = c->d_da;
+  c->tab.dg = c->d_dg;
+  c->tab.dz = c->d_dz;
+  c->tab.ca = c64{alpha[0].re - alpha[n - 1].re, alpha[0].im - alpha[n - 1].im};
+  c->tab.cg = c64{gamma[0].re - gamma[n - 1].re, gamma[0].im - gamma[n - 1].im};
+  c->tab.cz = c64{zc[0].re - zc[n - 1].re, zc[0].im - zc[n - 1].im};
+  c->tab.mu = mod->mu;
+  c->tab.beta = cont->beta;
+  c->tab.cos_et = c->d_cos;
+  c->tab.sin_et = c->d_sin;
+  c->tab.t_pos = c->d_tpos;
+
+  size_t bb = (size_t)24 << 30;
+  if (const char* s = getenv("FKDMFT_BATCH_BYTES")) {
+    const double v = atof(s);
+    if (v > 0) bb = (size_t)v;
+  }
+  c->batch_bytes = bb;
+  *out = c;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_destroy(fk_ctx* c) {
+  if (!c) return FK_OK;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  free_ctx(c);
+  delete c;
+  return FK_OK;
+}
+
+extern "C" const char* fk_last_error(const fk_ctx* c) {
+  return c ? c->err.c_str() : "NULL context";
+}
+
+extern "C" fk_status fk_dims(const fk_ctx* c, int* n_t, int* n_tau, int* n_c) {
+  if (!c) return FK_EINVAL;
+  if (n_t) *n_t = c->ci.n_t;
+  if (n_tau) *n_tau = c->ci.n_tau;
+  if (n_c) *n_c = c->ci.n_c;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_contour_points(const fk_ctx* c, double* z, double* W) {
+  if (!c) return FK_EINVAL;
+  int dims[3];
+  return fk_contour_build(&c->c, dims, z, W);
+}
+
+extern "C" fk_status fk_points(const fk_ctx* c, int* n_points, double* eps,
+                               double* ebar, double* rho) {
+  if (!c) return FK_EINVAL;
+  if (n_points) *n_points = c->npts;
+  for (int k = 0; k < c->npts; ++k) {
+    if (eps) eps[k] = c->eps[k];
+    if (ebar) ebar[k] = c->ebar[k];
+    if (rho) rho[k] = c->rho[k];
+  }
+  return FK_OK;
+}
+
+extern "C" fk_status fk_set_batch(fk_ctx* c, int batch, int* used) {
+  if (!c || batch < 0) return FK_EINVAL;
+  c->want_batch = batch;
+  batch_free(c->b64);
+  batch_free(c->b32);
+  fk_status s = ensure_batch<double>(c);
+  if (s != FK_OK) return s;
+  if (used) *used = c->b64.cap;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_set_sigma(fk_ctx* c, const double* sigma, int on_device) {
+  if (!c) return FK_EINVAL;
+  return copy_matrix_in(c, c->d_sigma, sigma, on_device);
+}
+
+extern "C" fk_status fk_get_sigma(const fk_ctx* cc, double* sigma, int on_device) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c) return FK_EINVAL;
+  return copy_matrix_out(c, sigma, c->d_sigma, on_device);
+}
+
+extern "C" fk_status fk_get_gloc(const fk_ctx* cc, double* gloc, int on_device) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c) return FK_EINVAL;
+  if (!c->have_gloc) return set_err(c, FK_ESTATE, "no lattice step yet");
+  return copy_matrix_out(c, gloc, c->d_gloc, on_device);
+}
+
+extern "C" fk_status fk_set_refinement(fk_ctx* c, int ir_steps) {
+  if (!c || ir_steps < 0 || ir_steps > 4) return FK_EINVAL;
+  c->ir_steps = ir_steps;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_set_switch(fk_ctx* c, double switch_tol) {
+  if (!c || !(switch_tol >= 0.0)) return FK_EINVAL;
+  c->switch_tol = switch_tol;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_compute_gloc(fk_ctx* c, fk_precision prec, double* ir_out) {
+  if (!c) return FK_EINVAL;
+  if (prec == FK_FP64) return lattice_step<double>(c, ir_out);
+  return set_err(c, FK_EINVAL, "precision %d not available", (int)prec);
+}
+
+extern "C" fk_status fk_get_current(const fk_ctx* cc, double* t, double* j,
+                                    double* n_t_out) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c) return FK_EINVAL;
+  if (!c->have_gloc) return set_err(c, FK_ESTATE, "no lattice step yet");
+  const int n_t = c->ci.n_t, n = c->ci.n_c;
+  if (t)
+    for (int i = 0; i < n_t; ++i) t[i] = c->ci.zr[i];
+  if (j) {
+    HIPCHK(c, hipMemcpyAsync(j, c->d_cur, sizeof(double) * n_t,
+                             hipMemcpyDeviceToHost, c->st));
+  }
+  if (n_t_out) {
+    // n(t_i) = Re[-i G_loc[i][2 N_t - i]] = Im G_loc[i][2 N_t - i]
+    std::vector<c64> row(1);
+    for (int i = 0; i < n_t; ++i) {
+      HIPCHK(c, hipMemcpyAsync(row.data(), c->d_gloc + (size_t)i * n + (2 * n_t - i),
+                               sizeof(c64), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+      n_t_out[i] = row[0].im;
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return FK_OK;
+}
+
+extern "C" fk_status fk_impurity_update(fk_ctx* c, double* max_dsigma_out) {
+  if (!c) return FK_EINVAL;
+  return impurity(c, max_dsigma_out);
+}
+
+extern "C" fk_status fk_iterate(fk_ctx* c, int max_iter, double tol,
+                                fk_precision prec, int* iters_out,
+                                double* delta_out, double* hist) {
+  if (!c || max_iter < 1) return FK_EINVAL;
+  const size_t mat = sizeof(c64) * (size_t)c->ci.n_c * c->ci.n_c;
+  double delta = std::numeric_limits<double>::infinity();
+  bool low = (prec == FK_MIXED);
+  int it = 0;
+  for (it = 1; it <= max_iter; ++it) {
+    fk_status s = fk_compute_gloc(c, low ? FK_MIXED : FK_FP64, nullptr);
+    if (s != FK_OK) return s;
+    if (it > 1) {
+      HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
+      HIPCHK(c, launch_maxabs(c->d_gloc, c->d_gprev, (size_t)c->ci.n_c * c->ci.n_c,
+                              c->d_key, c->st));
+      delta = read_key(c, &s);
+      if (s != FK_OK) return s;
+    }
+    if (hist) hist[it - 1] = delta;
+    HIPCHK(c, hipMemcpyAsync(c->d_gprev, c->d_gloc, mat, hipMemcpyDeviceToDevice,
+                             c->st));
+    s = impurity(c, nullptr);
+    if (s != FK_OK) return s;
+    if (low && delta < c->switch_tol) low = false;
+    if (delta < tol) break;
+  }
+  if (it > max_iter) it = max_iter;
+  if (iters_out) *iters_out = it;
+  if (delta_out) *delta_out = delta;
+  if (tol > 0.0 && !(delta < tol))
+    return set_err(c, FK_ENOTCONV, "not converged after %d iterations (delta %.3e)",
+                   max_iter, delta);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_timings(const fk_ctx* c, double* out7) {
+  if (!c || !out7) return FK_EINVAL;
+  for (int i = 0; i < 7; ++i) out7[i] = c->times[i];
+  return FK_OK;
+}

@@ -1,0 +1,55 @@
+// Launchers of the lattice-step and impurity kernels (fk_lattice.hip).
+#pragma once
+
+#include "fk_internal.h"
+
+namespace fk {
+
+// Device tables shared by all points of one context.  Per point k: eps, ebar,
+// rho.  Per contour point i >= 1: da/dg/dz = differences of the antiderivative
+// tables alpha, gamma and of z between points i and i-1 (complex).  Corner
+// differences ca/cg/cz = value at point 0 minus value at point N_c - 1.
+// Upper-branch tables (i < N_t): cos(E t_i), sin(E t_i), t_i > 0.
+struct PointTables {
+  const double* eps;
+  const double* ebar;
+  const double* rho;
+  const c64* da;
+  const c64* dg;
+  const c64* dz;
+  c64 ca, cg, cz;
+  double mu, beta;
+  const double* cos_et;
+  const double* sin_et;
+  const int* t_pos;
+};
+
+hipError_t launch_sigma_weight(const c64* sigma, const c64* w, c64* sigt, int n,
+                               hipStream_t st);
+template <typename TO>
+hipError_t launch_build(const c64* sigt, const PointTables& tab, int k0,
+                        int nmat, cplx<TO>* xbuf, size_t mat_stride, int ld,
+                        int n, hipStream_t st);
+template <typename TI>
+hipError_t launch_reduce(const cplx<TI>* xbuf, size_t mat_stride, int ld,
+                         const int* piv, const int* rowcol, int istride,
+                         const double* coef, int nmat, int n, c64* out,
+                         int accumulate, hipStream_t st);
+template <typename TI>
+hipError_t launch_current(const cplx<TI>* xbuf, size_t mat_stride, int ld,
+                          const int* piv, const int* rowcol, int istride,
+                          const PointTables& tab, int k0, int nmat, int n_t,
+                          double* cur, hipStream_t st);
+hipError_t launch_maxabs(const c64* a, const c64* b, size_t total,
+                         unsigned long long* key, hipStream_t st);
+hipError_t launch_right_weight(const c64* src, const c64* w, c64* dst, int ld,
+                               int n, hipStream_t st);
+hipError_t launch_add_right_weighted(c64* g0inv, const c64* sigma, const c64* w,
+                                     int n, hipStream_t st);
+hipError_t launch_shifted_pair(const c64* g0inv, double d0, double d1, c64* x0,
+                               c64* x1, int ld, int n, hipStream_t st);
+hipError_t launch_sigma_new(const c64* g0inv, const c64* ginv, const c64* w,
+                            c64* sigma, int n, unsigned long long* key,
+                            hipStream_t st);
+
+}  // namespace fk

@@ -1,0 +1,378 @@
+// Lattice-step kernels around the batched inversion (gfx950):
+//   build      A_k = G0_k^-1 - W Sigma W, with the exact sparse G0_k^-1 of the
+//              sampled noninteracting function (Sec. II, eq. g_contour_non_final2)
+//   reduce     G_loc += sum_k rho_k G_k            (eq. g_loc), fixed order
+//   current    j(t_i) += sum_k rho_k ebar_k(t_i) Re[i G_k[i, 2N_t - i]]   (eq. current_def)
+//   norms      max |A - B| and non-finite detection
+//   impurity   the elementwise pieces of the Falicov-Kimball update
+//              (eqs. effective_medium, dynamical_mean_field, g_imp_solve)
+// All of them are HBM-streaming kernels: consecutive threads touch consecutive
+// complex elements of a row.
+#include "fk_internal.h"
+#include "fk_kernels.h"
+
+namespace fk {
+
+// ------------------------------------------------------------ Sigma_t ------
+// sigt[i][j] = W_i sigma[i][j] W_j  (both contour integrals of eq. dyson)
+__global__ void k_sigma_weight(const c64* __restrict__ sigma,
+                               const c64* __restrict__ w, c64* __restrict__ sigt,
+                               int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e - (e / n) * n);
+    const c64 s = sigma[e], wi = w[i], wj = w[j];
+    c64 t;
+    t.re = wi.re * s.re - wi.im * s.im;
+    t.im = wi.re * s.im + wi.im * s.re;
+    c64 r;
+    r.re = t.re * wj.re - t.im * wj.im;
+    r.im = t.re * wj.im + t.im * wj.re;
+    sigt[e] = r;
+  }
+}
+
+// -------------------------------------------------------------- build ------
+// Per point k: the subdiagonal of G0_k^-1 is -i exp(-i q_i) with
+// q_i = eps da_i + ebar dg_i - mu dz_i (differences of the antiderivative
+// tables between contour points i and i-1), the diagonal is i, and the corner
+// (0, N-1) is i exp(-beta (eps - mu) - i q_c), q_c = eps (a_0 - a_{N-1}) +
+// ebar (g_0 - g_{N-1}) - mu (z_0 - z_{N-1}).
+__device__ inline c64 cexp_minus_i(c64 q, double extra_real) {
+  // exp(-i q + extra_real) for complex q = a + i b: exp(b + extra) (cos a - i sin a)
+  const double m = exp(q.im + extra_real);
+  double s, c;
+  sincos(q.re, &s, &c);
+  c64 r;
+  r.re = m * c;
+  r.im = -m * s;
+  return r;
+}
+
+template <typename TO>
+__global__ void k_build(const c64* __restrict__ sigt,
+                        const PointTables tab, int k0, int nmat,
+                        cplx<TO>* __restrict__ xbuf, size_t mat_stride, int ld,
+                        int n) {
+  const size_t per = (size_t)n * n;
+  const size_t total = per * nmat;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int m = (int)(e / per);
+    const size_t f = e - (size_t)m * per;
+    const int i = (int)(f / n), j = (int)(f - (f / n) * n);
+    const c64 s = sigt[f];
+    c64 a;
+    a.re = -s.re;
+    a.im = -s.im;
+    if (j == i) {
+      a.im += 1.0;
+    } else if (j == i - 1 || (i == 0 && j == n - 1)) {
+      const int k = k0 + m;
+      const double eps = tab.eps[k], ebar = tab.ebar[k];
+      c64 q;
+      double extra = 0.0;
+      if (j == i - 1) {
+        const c64 da = tab.da[i], dg = tab.dg[i], dz = tab.dz[i];
+        q.re = eps * da.re + ebar * dg.re - tab.mu * dz.re;
+        q.im = eps * da.im + ebar * dg.im - tab.mu * dz.im;
+        const c64 ex = cexp_minus_i(q, 0.0);
+        a.re += ex.im;   // -i * ex
+        a.im += -ex.re;
+      } else {
+        q.re = eps * tab.ca.re + ebar * tab.cg.re - tab.mu * tab.cz.re;
+        q.im = eps * tab.ca.im + ebar * tab.cg.im - tab.mu * tab.cz.im;
+        extra = -tab.beta * (eps - tab.mu);
+        const c64 ex = cexp_minus_i(q, extra);
+        a.re += -ex.im;  // +i * ex
+        a.im += ex.re;
+      }
+    }
+    cplx<TO> o;
+    o.re = (TO)a.re;
+    o.im = (TO)a.im;
+    xbuf[(size_t)m * mat_stride + (size_t)i * ld + j] = o;
+  }
+}
+
+// ------------------------------------------------------------- reduce ------
+// out[a][b] += sum_m coef[m] X_m[piv_m[a]][rowcol_m[b]]   (m in fixed order)
+template <typename TI>
+__global__ void k_reduce(const cplx<TI>* __restrict__ xbuf, size_t mat_stride,
+                         int ld, const int* __restrict__ pivbuf,
+                         const int* __restrict__ rowcolbuf, int istride,
+                         const double* __restrict__ coef, int nmat, int n,
+                         c64* __restrict__ out, int accumulate) {
+  const int a = blockIdx.y;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n;
+       b += gridDim.x * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int m = 0; m < nmat; ++m) {
+      const int r = pivbuf[(size_t)m * istride + a];
+      const int c = rowcolbuf[(size_t)m * istride + b];
+      if (r < 0 || c < 0 || r >= n || c >= n) {  // incomplete inversion
+        re = im = __builtin_nan("");
+        continue;
+      }
+      const cplx<TI> v = xbuf[(size_t)m * mat_stride + (size_t)r * ld + c];
+      const double w = coef[m];
+      re += w * (double)v.re;
+      im += w * (double)v.im;
+    }
+    c64 o = accumulate ? out[(size_t)a * n + b] : c64{0.0, 0.0};
+    o.re += re;
+    o.im += im;
+    out[(size_t)a * n + b] = o;
+  }
+}
+
+// j(t_i) += sum_m rho_m vel_m(i) Re[i G_m[i][2 n_t - i]],
+// vel_m(i) = ebar cos(E t_i) + eps sin(E t_i) for t_i > 0, else ebar.
+template <typename TI>
+__global__ void k_current(const cplx<TI>* __restrict__ xbuf, size_t mat_stride,
+                          int ld, const int* __restrict__ pivbuf,
+                          const int* __restrict__ rowcolbuf, int istride,
+                          const PointTables tab, int k0, int nmat, int n_t,
+                          double* __restrict__ cur) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_t) return;
+  const int pcol = 2 * n_t - i;
+  const double ct = tab.cos_et[i], st = tab.sin_et[i];
+  const bool on = tab.t_pos[i] != 0;
+  double acc = 0.0;
+  for (int m = 0; m < nmat; ++m) {
+    const int k = k0 + m;
+    const int r = pivbuf[(size_t)m * istride + i];
+    const int c = rowcolbuf[(size_t)m * istride + pcol];
+    if (r < 0 || c < 0 || r >= istride || c >= istride) {
+      acc = __builtin_nan("");
+      continue;
+    }
+    const cplx<TI> v = xbuf[(size_t)m * mat_stride + (size_t)r * ld + c];
+    const double vel = on ? tab.ebar[k] * ct + tab.eps[k] * st : tab.ebar[k];
+    acc += tab.rho[k] * vel * (-(double)v.im);  // Re[i g] = -Im g
+  }
+  cur[i] += acc;
+}
+
+// -------------------------------------------------------------- norms ------
+// bits of the max of |a - b| (or |a| when b == nullptr) as an unsigned 64-bit
+// key: non-negative doubles order like their bit patterns, NaN above +Inf.
+__global__ void k_maxabs(const c64* __restrict__ a, const c64* __restrict__ b,
+                         size_t total, unsigned long long* __restrict__ key) {
+  double m = 0.0;
+  bool bad = false;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    c64 d = a[e];
+    if (b) {
+      d.re -= b[e].re;
+      d.im -= b[e].im;
+    }
+    const double v = sqrt(d.re * d.re + d.im * d.im);
+    if (!(v <= 1.79769313486231570815e308)) bad = true;
+    else if (v > m) m = v;
+  }
+  unsigned long long k = bad ? 0x7ff8000000000000ULL
+                             : (unsigned long long)__double_as_longlong(m);
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(k, off);
+    k = o > k ? o : k;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(key, k);
+}
+
+// ----------------------------------------------------------- impurity ------
+// dst[i][j] = src[i][j] * W_j  (right weighting), stored into an inversion slot
+__global__ void k_right_weight(const c64* __restrict__ src,
+                               const c64* __restrict__ w, c64* __restrict__ dst,
+                               int ld, int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e - (e / n) * n);
+    const c64 s = src[e], wj = w[j];
+    c64 r;
+    r.re = s.re * wj.re - s.im * wj.im;
+    r.im = s.re * wj.im + s.im * wj.re;
+    dst[(size_t)i * ld + j] = r;
+  }
+}
+
+// g0inv += sigma * W (right-weighted Sigma added to the inverse already there)
+__global__ void k_add_right_weighted(c64* __restrict__ g0inv,
+                                     const c64* __restrict__ sigma,
+                                     const c64* __restrict__ w, int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e - (e / n) * n);
+    const c64 s = sigma[e], wj = w[j];
+    c64 g = g0inv[e];
+    g.re += s.re * wj.re - s.im * wj.im;
+    g.im += s.re * wj.im + s.im * wj.re;
+    g0inv[e] = g;
+  }
+}
+
+// slot_m = g0inv + d_m S for m = 0, 1 (S[j][j-1] = 1, S[0][n-1] = -1)
+__global__ void k_shifted_pair(const c64* __restrict__ g0inv, double d0,
+                               double d1, c64* __restrict__ x0,
+                               c64* __restrict__ x1, int ld, int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e - (e / n) * n);
+    double s = 0.0;
+    if (j == i - 1) s = 1.0;
+    if (i == 0 && j == n - 1) s = (n == 1) ? 0.0 : -1.0;
+    c64 a = g0inv[e], b = g0inv[e];
+    a.re += d0 * s;
+    b.re += d1 * s;
+    x0[(size_t)i * ld + j] = a;
+    x1[(size_t)i * ld + j] = b;
+  }
+}
+
+// sigma_new[i][j] = (g0inv[i][j] - ginv[i][j]) / W_j, and the running max of
+// |sigma_new - sigma_old| via the key of k_maxabs.
+__global__ void k_sigma_new(const c64* __restrict__ g0inv,
+                            const c64* __restrict__ ginv,
+                            const c64* __restrict__ w, c64* __restrict__ sigma,
+                            int n, unsigned long long* __restrict__ key) {
+  const size_t total = (size_t)n * n;
+  double mx = 0.0;
+  bool bad = false;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e - (e / n) * n);
+    c64 d;
+    d.re = g0inv[e].re - ginv[e].re;
+    d.im = g0inv[e].im - ginv[e].im;
+    const c64 wj = w[j];
+    const double den = wj.re * wj.re + wj.im * wj.im;
+    c64 s;
+    s.re = (d.re * wj.re + d.im * wj.im) / den;
+    s.im = (d.im * wj.re - d.re * wj.im) / den;
+    const c64 old = sigma[e];
+    const double dr = s.re - old.re, di = s.im - old.im;
+    const double v = sqrt(dr * dr + di * di);
+    if (!(v <= 1.79769313486231570815e308)) bad = true;
+    else if (v > mx) mx = v;
+    sigma[e] = s;
+  }
+  unsigned long long k = bad ? 0x7ff8000000000000ULL
+                             : (unsigned long long)__double_as_longlong(mx);
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(k, off);
+    k = o > k ? o : k;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(key, k);
+}
+
+// ------------------------------------------------------------ launchers ----
+static inline int grid_for(size_t total, int block) {
+  size_t g = (total + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_sigma_weight(const c64* sigma, const c64* w, c64* sigt, int n,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_sigma_weight, dim3(grid_for((size_t)n * n, 256)),
+                     dim3(256), 0, st, sigma, w, sigt, n);
+  return hipGetLastError();
+}
+
+template <typename TO>
+hipError_t launch_build(const c64* sigt, const PointTables& tab, int k0,
+                        int nmat, cplx<TO>* xbuf, size_t mat_stride, int ld,
+                        int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_build<TO>, dim3(grid_for((size_t)n * n * nmat, 256)),
+                     dim3(256), 0, st, sigt, tab, k0, nmat, xbuf, mat_stride,
+                     ld, n);
+  return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t launch_reduce(const cplx<TI>* xbuf, size_t mat_stride, int ld,
+                         const int* piv, const int* rowcol, int istride,
+                         const double* coef, int nmat, int n, c64* out,
+                         int accumulate, hipStream_t st) {
+  const int bx = (n + 255) / 256;
+  hipLaunchKernelGGL(k_reduce<TI>, dim3(bx, n), dim3(256), 0, st, xbuf,
+                     mat_stride, ld, piv, rowcol, istride, coef, nmat, n, out,
+                     accumulate);
+  return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t launch_current(const cplx<TI>* xbuf, size_t mat_stride, int ld,
+                          const int* piv, const int* rowcol, int istride,
+                          const PointTables& tab, int k0, int nmat, int n_t,
+                          double* cur, hipStream_t st) {
+  hipLaunchKernelGGL(k_current<TI>, dim3((n_t + 127) / 128), dim3(128), 0, st,
+                     xbuf, mat_stride, ld, piv, rowcol, istride, tab, k0, nmat,
+                     n_t, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxabs(const c64* a, const c64* b, size_t total,
+                         unsigned long long* key, hipStream_t st) {
+  hipLaunchKernelGGL(k_maxabs, dim3(grid_for(total, 256) > 2048 ? 2048 : grid_for(total, 256)),
+                     dim3(256), 0, st, a, b, total, key);
+  return hipGetLastError();
+}
+
+hipError_t launch_right_weight(const c64* src, const c64* w, c64* dst, int ld,
+                               int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_right_weight, dim3(grid_for((size_t)n * n, 256)),
+                     dim3(256), 0, st, src, w, dst, ld, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_right_weighted(c64* g0inv, const c64* sigma, const c64* w,
+                                     int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_right_weighted, dim3(grid_for((size_t)n * n, 256)),
+                     dim3(256), 0, st, g0inv, sigma, w, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_shifted_pair(const c64* g0inv, double d0, double d1, c64* x0,
+                               c64* x1, int ld, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_shifted_pair, dim3(grid_for((size_t)n * n, 256)),
+                     dim3(256), 0, st, g0inv, d0, d1, x0, x1, ld, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_new(const c64* g0inv, const c64* ginv, const c64* w,
+                            c64* sigma, int n, unsigned long long* key,
+                            hipStream_t st) {
+  const int g = grid_for((size_t)n * n, 256);
+  hipLaunchKernelGGL(k_sigma_new, dim3(g > 2048 ? 2048 : g), dim3(256), 0, st,
+                     g0inv, ginv, w, sigma, n, key);
+  return hipGetLastError();
+}
+
+template hipError_t launch_build<double>(const c64*, const PointTables&, int,
+                                         int, c64*, size_t, int, int,
+                                         hipStream_t);
+template hipError_t launch_build<float>(const c64*, const PointTables&, int,
+                                        int, c32*, size_t, int, int,
+                                        hipStream_t);
+template hipError_t launch_reduce<double>(const c64*, size_t, int, const int*,
+                                          const int*, int, const double*, int,
+                                          int, c64*, int, hipStream_t);
+template hipError_t launch_reduce<float>(const c32*, size_t, int, const int*,
+                                         const int*, int, const double*, int,
+                                         int, c64*, int, hipStream_t);
+template hipError_t launch_current<double>(const c64*, size_t, int, const int*,
+                                           const int*, int, const PointTables&,
+                                           int, int, int, double*, hipStream_t);
+template hipError_t launch_current<float>(const c32*, size_t, int, const int*,
+                                          const int*, int, const PointTables&,
+                                          int, int, int, double*, hipStream_t);
+
+}  // namespace fk

@@ -1,0 +1,268 @@
+"""ctypes binding of libfkdmft.so (C ABI in include/fkdmft.h).
+
+Argument marshalling only: every step of the lattice step, the impurity update
+and the loop runs in the HIP library.  Loading fails loudly when the library has
+not been built; there is no fallback.
+
+Host matrices are numpy complex128 arrays (N_c x N_c, C order).  Device
+matrices may be passed as torch tensors (complex128, on the context's device,
+contiguous): their data_ptr() is handed to the library with on_device = 1.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfkdmft.so")
+
+FK_OK, FK_EINVAL, FK_ENOMEM, FK_EDEVICE = 0, -1, -2, -3
+FK_ESINGULAR, FK_ENONFINITE, FK_ENOTCONV, FK_ESTATE = -4, -5, -6, -7
+FK_FP64, FK_MIXED = 0, 1
+CONVENTION = {"symmetric": 0, "paper": 1}
+
+
+class FkError(RuntimeError):
+    def __init__(self, status, detail=""):
+        self.status = status
+        super().__init__(f"{status_string(status)}: {detail}")
+
+
+class Contour(ctypes.Structure):
+    _fields_ = [("t_min", ctypes.c_double), ("t_max", ctypes.c_double),
+                ("dt", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("beta", ctypes.c_double)]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_double), ("E", ctypes.c_double),
+                ("mu", ctypes.c_double), ("w1", ctypes.c_double),
+                ("n_eps", ctypes.c_int), ("n_ebar", ctypes.c_int),
+                ("convention", ctypes.c_int), ("gh_average", ctypes.c_int)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_vp = ctypes.c_void_p
+
+# name: (restype, argtypes) for every entry point of include/fkdmft.h
+SIGNATURES = {
+    "fk_gauss_hermite": (ctypes.c_int, [ctypes.c_int, _dp, _dp]),
+    "fk_contour_build": (ctypes.c_int, [ctypes.POINTER(Contour), _ip, _dp, _dp]),
+    "fk_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fk_create": (ctypes.c_int, [ctypes.POINTER(Contour), ctypes.POINTER(Model),
+                                 _vp, ctypes.POINTER(_vp)]),
+    "fk_destroy": (ctypes.c_int, [_vp]),
+    "fk_last_error": (ctypes.c_char_p, [_vp]),
+    "fk_dims": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
+    "fk_contour_points": (ctypes.c_int, [_vp, _dp, _dp]),
+    "fk_points": (ctypes.c_int, [_vp, _ip, _dp, _dp, _dp]),
+    "fk_set_batch": (ctypes.c_int, [_vp, ctypes.c_int, _ip]),
+    "fk_set_sigma": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "fk_get_sigma": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "fk_get_gloc": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "fk_compute_gloc": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "fk_set_refinement": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "fk_get_current": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "fk_impurity_update": (ctypes.c_int, [_vp, _dp]),
+    "fk_iterate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                  _ip, _dp, _dp]),
+    "fk_set_switch": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "fk_timings": (ctypes.c_int, [_vp, _dp]),
+}
+
+_lib = None
+
+
+def library():
+    """Load libfkdmft.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing; build the HIP library "
+                "(python -c 'import __graft_entry__ as g; g.build()')")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def status_string(s):
+    return library().fk_status_string(s).decode()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def gauss_hermite(n):
+    x = np.zeros(max(n, 1))
+    w = np.zeros(max(n, 1))
+    s = library().fk_gauss_hermite(n, _dptr(x), _dptr(w))
+    if s != FK_OK:
+        raise FkError(s, f"gauss_hermite({n})")
+    return x, w
+
+
+def contour_build(t_min, t_max, dt, dtau, beta):
+    c = Contour(t_min, t_max, dt, dtau, beta)
+    dims = (ctypes.c_int * 3)()
+    s = library().fk_contour_build(ctypes.byref(c), dims, None, None)
+    if s != FK_OK:
+        raise FkError(s, "contour")
+    n = dims[2]
+    z = np.zeros(2 * n)
+    w = np.zeros(2 * n)
+    library().fk_contour_build(ctypes.byref(c), dims, _dptr(z), _dptr(w))
+    return (dims[0], dims[1], dims[2]), z.view(np.complex128), w.view(np.complex128)
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class Context:
+    """One fk_ctx.  stream: a torch.cuda.Stream, an int hipStream_t, or None."""
+
+    def __init__(self, t_min, t_max, dt, dtau, beta, U, E, mu=0.0, w1=0.5,
+                 n_eps=10, n_ebar=10, convention="symmetric", stream=None):
+        lib = library()
+        self._lib = lib
+        c = Contour(t_min, t_max, dt, dtau, beta)
+        m = Model(U, E, mu, w1, n_eps, n_ebar, CONVENTION[convention], 0)
+        if stream is None:
+            sp = None
+        elif isinstance(stream, int):
+            sp = stream
+        else:
+            sp = stream.cuda_stream
+        h = _vp()
+        s = lib.fk_create(ctypes.byref(c), ctypes.byref(m), sp, ctypes.byref(h))
+        if s != FK_OK:
+            raise FkError(s, "fk_create")
+        self._h = h
+        nt, ntau, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lib.fk_dims(h, ctypes.byref(nt), ctypes.byref(ntau), ctypes.byref(nc))
+        self.n_t, self.n_tau, self.n_c = nt.value, ntau.value, nc.value
+
+    # -- plumbing
+    def _check(self, s, what):
+        if s != FK_OK:
+            raise FkError(s, f"{what}: {self._lib.fk_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- queries
+    def contour_points(self):
+        z = np.zeros(2 * self.n_c)
+        w = np.zeros(2 * self.n_c)
+        self._check(self._lib.fk_contour_points(self._h, _dptr(z), _dptr(w)),
+                    "fk_contour_points")
+        return z.view(np.complex128), w.view(np.complex128)
+
+    def points(self):
+        n = ctypes.c_int()
+        self._check(self._lib.fk_points(self._h, ctypes.byref(n), None, None, None),
+                    "fk_points")
+        e, eb, r = np.zeros(n.value), np.zeros(n.value), np.zeros(n.value)
+        self._check(self._lib.fk_points(self._h, ctypes.byref(n), _dptr(e),
+                                        _dptr(eb), _dptr(r)), "fk_points")
+        return e, eb, r
+
+    def set_batch(self, batch):
+        used = ctypes.c_int()
+        self._check(self._lib.fk_set_batch(self._h, batch, ctypes.byref(used)),
+                    "fk_set_batch")
+        return used.value
+
+    # -- state
+    def _matrix_arg(self, a, write):
+        if _is_torch(a):
+            assert a.is_contiguous() and tuple(a.shape) == (self.n_c, self.n_c)
+            return a.data_ptr(), 1, None
+        if write:
+            arr = a
+            assert arr.dtype == np.complex128 and arr.flags.c_contiguous
+            assert arr.shape == (self.n_c, self.n_c)
+        else:
+            arr = np.ascontiguousarray(a, dtype=np.complex128)
+            assert arr.shape == (self.n_c, self.n_c)
+        return arr.ctypes.data, 0, arr
+
+    def set_sigma(self, sigma):
+        p, dev, keep = self._matrix_arg(sigma, False)
+        self._check(self._lib.fk_set_sigma(self._h, p, dev), "fk_set_sigma")
+
+    def get_sigma(self, out=None):
+        out = np.zeros((self.n_c, self.n_c), np.complex128) if out is None else out
+        p, dev, _ = self._matrix_arg(out, True)
+        self._check(self._lib.fk_get_sigma(self._h, p, dev), "fk_get_sigma")
+        return out
+
+    def get_gloc(self, out=None):
+        out = np.zeros((self.n_c, self.n_c), np.complex128) if out is None else out
+        p, dev, _ = self._matrix_arg(out, True)
+        self._check(self._lib.fk_get_gloc(self._h, p, dev), "fk_get_gloc")
+        return out
+
+    # -- hot path
+    def compute_gloc(self, precision=FK_FP64):
+        r = ctypes.c_double()
+        self._check(self._lib.fk_compute_gloc(self._h, precision, ctypes.byref(r)),
+                    "fk_compute_gloc")
+        return r.value
+
+    def set_refinement(self, steps):
+        self._check(self._lib.fk_set_refinement(self._h, steps), "fk_set_refinement")
+
+    def set_switch(self, tol):
+        self._check(self._lib.fk_set_switch(self._h, tol), "fk_set_switch")
+
+    def get_current(self):
+        t, j, n = np.zeros(self.n_t), np.zeros(self.n_t), np.zeros(self.n_t)
+        self._check(self._lib.fk_get_current(self._h, _dptr(t), _dptr(j), _dptr(n)),
+                    "fk_get_current")
+        return t, j, n
+
+    def impurity_update(self):
+        d = ctypes.c_double()
+        self._check(self._lib.fk_impurity_update(self._h, ctypes.byref(d)),
+                    "fk_impurity_update")
+        return d.value
+
+    def iterate(self, max_iter, tol=0.0, precision=FK_FP64):
+        it = ctypes.c_int()
+        d = ctypes.c_double()
+        hist = np.zeros(max_iter)
+        s = self._lib.fk_iterate(self._h, max_iter, tol, precision, ctypes.byref(it),
+                                 ctypes.byref(d), _dptr(hist))
+        if s not in (FK_OK, FK_ENOTCONV):
+            self._check(s, "fk_iterate")
+        return dict(iters=it.value, delta=d.value, history=hist[:it.value],
+                    converged=(s == FK_OK))
+
+    def timings(self):
+        out = np.zeros(7)
+        self._check(self._lib.fk_timings(self._h, _dptr(out)), "fk_timings")
+        return dict(build_ms=out[0], invert_ms=out[1], refine_ms=out[2],
+                    reduce_ms=out[3], impurity_ms=out[4], launches=int(out[5]),
+                    step_kernels_ms=out[6])
