@@ -271,11 +271,14 @@ template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
 }
 
 // Invert matrices 0..nmat-1 of the batch in place (permuted storage).
+// ev_steps (nullable) brackets the step kernels alone.
 template <typename T>
-hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, int* launches) {
+hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, int* launches,
+                        hipEvent_t* ev_steps = nullptr) {
   hipError_t e;
   if ((e = fill_int(b.rowcol, -1, (size_t)b.n * nmat, st)) != hipSuccess) return e;
   if ((e = fill_int(b.status, 0, (size_t)nmat, st)) != hipSuccess) return e;
+  if (ev_steps && (e = hipEventRecord(ev_steps[0], st)) != hipSuccess) return e;
   for (int s = -1; s < b.nsteps; ++s) {
     const int nitems = nmat * b.cnt[s + 1];
     if (nitems == 0) continue;
@@ -285,6 +288,7 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, int* launches) {
     if (e != hipSuccess) return e;
     if (launches) ++*launches;
   }
+  if (ev_steps && (e = hipEventRecord(ev_steps[1], st)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -439,7 +443,7 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
     HIPCHK(c, launch_build<T>(c->d_sigt, c->tab, k0, nmat, b.x, b.stride, b.ld,
                               n, c->st));
     HIPCHK(c, hipEventRecord(c->ev[1], c->st));
-    HIPCHK(c, batch_invert<T>(b, nmat, c->st, &launches));
+    HIPCHK(c, batch_invert<T>(b, nmat, c->st, &launches, &c->ev[6]));
     HIPCHK(c, hipEventRecord(c->ev[2], c->st));
     HIPCHK(c, launch_reduce<T>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                c->d_rho + k0, nmat, n, c->d_gloc, k0 > 0 ? 1 : 0,
@@ -452,6 +456,7 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
     c->times[0] += elapsed(c->ev[0], c->ev[1]);
     c->times[1] += elapsed(c->ev[1], c->ev[2]);
     c->times[3] += elapsed(c->ev[2], c->ev[3]);
+    c->times[6] += elapsed(c->ev[6], c->ev[7]);
   }
   c->times[5] = launches;
   // non-finite check of G_loc

@@ -70,12 +70,31 @@ __device__ void update_stripe(cplx<T>* __restrict__ x, int ld, int n,
   const int c0 = q * kNB;
   const int cw = min(kNB, n - c0);
 
-  // old pivot rows of this stripe; zero-padded to kNB x kNB
-  for (int e = tid; e < kNB * kNB; e += kThreads) {
-    const int l = e / kNB, c = e - (e / kNB) * kNB;
-    cplx<T> v = {T(0), T(0)};
-    if (l < w && c < cw) v = x[(size_t)piv[j0 + l] * ld + c0 + c];
-    Bs[l * kPitch + c] = v;
+  // old pivot rows of this stripe; zero-padded to kNB x kNB.  All loads use
+  // clamped (in-range) addresses and are masked afterwards, so that they are
+  // issued together instead of one branch-guarded round trip at a time.
+  {
+    int pr[kNB * kNB / kThreads];
+#pragma unroll
+    for (int t = 0; t < kNB * kNB / kThreads; ++t) {
+      const int l = (tid + t * kThreads) / kNB;
+      pr[t] = piv[j0 + min(l, w - 1)];
+    }
+    cplx<T> bv[kNB * kNB / kThreads];
+#pragma unroll
+    for (int t = 0; t < kNB * kNB / kThreads; ++t) {
+      const int e = tid + t * kThreads;
+      const int c = e % kNB;
+      bv[t] = x[(size_t)pr[t] * ld + c0 + min(c, cw - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < kNB * kNB / kThreads; ++t) {
+      const int e = tid + t * kThreads;
+      const int l = e / kNB, c = e % kNB;
+      cplx<T> v = bv[t];
+      if (!(l < w && c < cw)) v.re = v.im = T(0);
+      Bs[l * kPitch + c] = v;
+    }
   }
 
   const int lane = tid & 63, wave = tid >> 6;
@@ -84,10 +103,39 @@ __device__ void update_stripe(cplx<T>* __restrict__ x, int ld, int n,
 
   for (int r0 = 0; r0 < n; r0 += kTM) {
     __syncthreads();  // Bs written / previous Ms consumed
-    for (int e = tid; e < kTM * kNB; e += kThreads) {
-      const int i = e / kNB, l = e - (e / kNB) * kNB;
-      cplx<T> v = {T(0), T(0)};
-      if (r0 + i < n && l < w) v = x[(size_t)(r0 + i) * ld + j0 + l];
+    constexpr int kML = kTM * kNB / kThreads;
+    cplx<T> mv[kML];
+#pragma unroll
+    for (int t = 0; t < kML; ++t) {
+      const int e = tid + t * kThreads;
+      const int i = e / kNB, l = e % kNB;
+      mv[t] = x[(size_t)min(r0 + i, n - 1) * ld + j0 + min(l, w - 1)];
+    }
+    int rcv[2][4];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
+        rcv[ii][v] = rowcol[min(row, n - 1)];
+      }
+    cplx<T> cv[2][2][4];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
+          const int col = 32 * wc + 16 * jj + li;
+          cv[ii][jj][v] = x[(size_t)min(row, n - 1) * ld + c0 + min(col, cw - 1)];
+        }
+#pragma unroll
+    for (int t = 0; t < kML; ++t) {
+      const int e = tid + t * kThreads;
+      const int i = e / kNB, l = e % kNB;
+      cplx<T> v = mv[t];
+      if (!(r0 + i < n && l < w)) v.re = v.im = T(0);
       Ms[i * kPitch + l] = v;
     }
     v4 cr[2][2], ci[2][2];
@@ -99,17 +147,10 @@ __device__ void update_stripe(cplx<T>* __restrict__ x, int ld, int n,
         for (int v = 0; v < 4; ++v) {
           const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
           const int col = 32 * wc + 16 * jj + li;
-          T re = T(0), im = T(0);
-          if (row < n && col < cw) {
-            const int rc = rowcol[row];
-            if (!(rc >= j0 && rc < j0 + w)) {
-              const cplx<T> c = x[(size_t)row * ld + c0 + col];
-              re = c.re;
-              im = c.im;
-            }
-          }
-          cr[ii][jj][v] = re;
-          ci[ii][jj][v] = im;
+          const int rc = rcv[ii][v];
+          const bool keep = row < n && col < cw && !(rc >= j0 && rc < j0 + w);
+          cr[ii][jj][v] = keep ? cv[ii][jj][v].re : T(0);
+          ci[ii][jj][v] = keep ? cv[ii][jj][v].im : T(0);
         }
     __syncthreads();  // Ms ready
 #pragma unroll 4
@@ -199,13 +240,17 @@ __device__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
     cplx<T> v[kRPT][kIB];
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
+      const int r = min(tid + i * kThreads, n - 1);
+#pragma unroll
+      for (int l = 0; l < kIB; ++l)
+        v[i][l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < kRPT; ++i) {
       const int r = tid + i * kThreads;
 #pragma unroll
-      for (int l = 0; l < kIB; ++l) {
-        cplx<T> t = {T(0), T(0)};
-        if (r < n && l < iw) t = x[(size_t)r * ld + c0 + b0 + l];
-        v[i][l] = t;
-      }
+      for (int l = 0; l < kIB; ++l)
+        if (!(r < n && l < iw)) v[i][l].re = v[i][l].im = T(0);
     }
 #pragma unroll
     for (int l = 0; l < kIB; ++l) {
@@ -320,24 +365,41 @@ __device__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
       Bo[e] = t;
     }
     __syncthreads();
-    // rank-iw update of the other panel columns (row-major, coalesced)
+    // rank-iw update of the other panel columns (row-major, coalesced); the
+    // loads of kBat elements are issued before any of them is stored.
+    constexpr int kBat = 8;
     const int total = n * cw;
-    for (int e = tid; e < total; e += kThreads) {
-      const int r = e / cw, c = e - (e / cw) * cw;
-      if (c >= b0 && c < b0 + iw) continue;
-      bool isp = false;
+    int pv0[kIB];
 #pragma unroll
-      for (int l = 0; l < kIB; ++l) isp |= (l < iw && pvt[l] == r);
-      cplx<T> acc = {T(0), T(0)};
-      if (!isp) acc = x[(size_t)r * ld + c0 + c];
+    for (int l = 0; l < kIB; ++l) pv0[l] = (l < iw) ? pvt[l] : -1;
+    for (int e0 = tid; e0 < total; e0 += kThreads * kBat) {
+      cplx<T> old[kBat];
 #pragma unroll
-      for (int l = 0; l < kIB; ++l) {
-        const cplx<T> mv = Mi[r * kIB + l];
-        const cplx<T> bv = Bo[l * kNB + c];
-        acc.re += mv.re * bv.re - mv.im * bv.im;
-        acc.im += mv.re * bv.im + mv.im * bv.re;
+      for (int b = 0; b < kBat; ++b) {
+        const int e = min(e0 + b * kThreads, total - 1);
+        const int r = e / cw, c = e - (e / cw) * cw;
+        old[b] = x[(size_t)r * ld + c0 + c];
       }
-      x[(size_t)r * ld + c0 + c] = acc;
+#pragma unroll
+      for (int b = 0; b < kBat; ++b) {
+        const int e = e0 + b * kThreads;
+        if (e >= total) break;
+        const int r = e / cw, c = e - (e / cw) * cw;
+        if (c >= b0 && c < b0 + iw) continue;
+        bool isp = false;
+#pragma unroll
+        for (int l = 0; l < kIB; ++l) isp |= (pv0[l] == r);
+        cplx<T> acc = old[b];
+        if (isp) acc.re = acc.im = T(0);
+#pragma unroll
+        for (int l = 0; l < kIB; ++l) {
+          const cplx<T> mm = Mi[r * kIB + l];
+          const cplx<T> bb = Bo[l * kNB + c];
+          acc.re += mm.re * bb.re - mm.im * bb.im;
+          acc.im += mm.re * bb.im + mm.im * bb.re;
+        }
+        x[(size_t)r * ld + c0 + c] = acc;
+      }
     }
     __syncthreads();
   }
