@@ -199,17 +199,21 @@ template <typename T> struct Batch {
   int cap = 0, n = 0, ld = 0;
   size_t stride = 0;
   cplx<T>* x = nullptr;
+  cplx<T>* bbuf = nullptr;     // gathered pivot rows, kNBO x ld per matrix
   int* piv = nullptr;
   int* rowcol = nullptr;
   int* status = nullptr;
   MatDesc* descs = nullptr;
-  WorkItem* items = nullptr;
-  std::vector<int> off, cnt;  // per step s = -1 .. nsteps-1 (index s+1)
-  int nsteps = 0;
+  TileItem* items = nullptr;
+  // per outer step S: tile items of the next block's columns ("narrow") and of
+  // all other columns ("big"), matrix-major so a prefix serves fewer matrices
+  std::vector<int> offN, cntN, offB, cntB;
+  int nouter = 0;
 };
 
 template <typename T> void batch_free(Batch<T>& b) {
   if (b.x) (void)hipFree(b.x);
+  if (b.bbuf) (void)hipFree(b.bbuf);
   if (b.piv) (void)hipFree(b.piv);
   if (b.rowcol) (void)hipFree(b.rowcol);
   if (b.status) (void)hipFree(b.status);
@@ -224,15 +228,18 @@ template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
   b.n = n;
   b.ld = n;
   b.stride = (size_t)n * n;
-  b.nsteps = (n + kNB - 1) / kNB;
+  b.nouter = (n + kNBO - 1) / kNBO;
   hipError_t e;
   if ((e = hipMalloc(&b.x, sizeof(cplx<T>) * b.stride * cap)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.bbuf, sizeof(cplx<T>) * (size_t)kNBO * b.ld * cap)) != hipSuccess)
+    return e;
   if ((e = hipMalloc(&b.piv, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
   if ((e = hipMalloc(&b.rowcol, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
   if ((e = hipMalloc(&b.status, sizeof(int) * cap)) != hipSuccess) return e;
   std::vector<MatDesc> d(cap);
   for (int m = 0; m < cap; ++m) {
     d[m].xoff = (long long)b.stride * m;
+    d[m].boff = (long long)kNBO * b.ld * m;
     d[m].n = n;
     d[m].ld = b.ld;
     d[m].ioff = n * m;
@@ -242,53 +249,85 @@ template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
   if ((e = hipMemcpy(b.descs, d.data(), sizeof(MatDesc) * cap,
                      hipMemcpyHostToDevice)) != hipSuccess)
     return e;
-  // Work items per step, matrix-major so that a prefix serves fewer matrices;
-  // the stripe that becomes the next panel comes first within each matrix.
-  const int ns = b.nsteps;
-  std::vector<WorkItem> it;
-  b.off.assign(ns + 1, 0);
-  b.cnt.assign(ns + 1, 0);
-  for (int s = -1; s < ns; ++s) {
-    b.off[s + 1] = (int)it.size();
-    int per = 0;
-    for (int m = 0; m < cap; ++m) {
-      std::vector<int> qs;
-      if (s < 0) {
-        qs.push_back(0);
-      } else {
-        if (s + 1 < ns) qs.push_back(s + 1);
-        for (int q = 0; q < ns; ++q)
-          if (q != s && q != s + 1) qs.push_back(q);
+  const int nt = (n + kTile - 1) / kTile;
+  std::vector<TileItem> it;
+  b.offN.assign(b.nouter, 0);
+  b.cntN.assign(b.nouter, 0);
+  b.offB.assign(b.nouter, 0);
+  b.cntB.assign(b.nouter, 0);
+  for (int S = 0; S < b.nouter; ++S) {
+    for (int pass = 0; pass < 2; ++pass) {
+      (pass ? b.offB : b.offN)[S] = (int)it.size();
+      int per = 0;
+      for (int m = 0; m < cap; ++m) {
+        per = 0;
+        for (int tc = 0; tc < nt; ++tc) {
+          const int blk = tc / (kNBO / kTile);
+          const bool narrow = blk == S + 1;
+          const bool big = blk != S && blk != S + 1;
+          if (pass == 0 ? !narrow : !big) continue;
+          for (int tr = 0; tr < nt; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
+          per += nt;
+        }
       }
-      for (int q : qs) it.push_back(WorkItem{m, q});
-      per = (int)qs.size();
+      (pass ? b.cntB : b.cntN)[S] = per;
     }
-    b.cnt[s + 1] = per;
   }
-  if ((e = hipMalloc(&b.items, sizeof(WorkItem) * it.size())) != hipSuccess) return e;
-  return hipMemcpy(b.items, it.data(), sizeof(WorkItem) * it.size(),
+  if ((e = hipMalloc(&b.items, sizeof(TileItem) * std::max<size_t>(it.size(), 1))) !=
+      hipSuccess)
+    return e;
+  if (it.empty()) return hipSuccess;
+  return hipMemcpy(b.items, it.data(), sizeof(TileItem) * it.size(),
                    hipMemcpyHostToDevice);
 }
 
-// Invert matrices 0..nmat-1 of the batch in place (permuted storage).
-// ev_steps (nullable) brackets the step kernels alone.
+// Side stream and events of the look-ahead (default priority).
+struct Aux {
+  hipStream_t st2 = nullptr;
+  hipEvent_t evN = nullptr, evP = nullptr;
+};
+
+// Invert matrices 0..nmat-1 of the batch in place (permuted storage).  The
+// next outer block is factored on the side stream while the big update of
+// the current block runs on st.  ev_steps (nullable) brackets the kernels.
 template <typename T>
-hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, int* launches,
-                        hipEvent_t* ev_steps = nullptr) {
+hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
+                        int* launches, hipEvent_t* ev_steps = nullptr) {
   hipError_t e;
   if ((e = fill_int(b.rowcol, -1, (size_t)b.n * nmat, st)) != hipSuccess) return e;
   if ((e = fill_int(b.status, 0, (size_t)nmat, st)) != hipSuccess) return e;
   if (ev_steps && (e = hipEventRecord(ev_steps[0], st)) != hipSuccess) return e;
-  for (int s = -1; s < b.nsteps; ++s) {
-    const int nitems = nmat * b.cnt[s + 1];
-    if (nitems == 0) continue;
-    const int grid = 8 * ((nitems + 7) / 8);
-    e = gje_step<T>(b.x, b.piv, b.rowcol, b.descs, b.items + b.off[s + 1],
-                    nitems, s, b.status, grid, st);
-    if (e != hipSuccess) return e;
-    if (launches) ++*launches;
+  int nl = 0;
+  if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, 0, b.status, st)) !=
+      hipSuccess)
+    return e;
+  ++nl;
+  for (int S = 0; S < b.nouter; ++S) {
+    const bool next = S + 1 < b.nouter;
+    if ((e = gje_gather<T>(b.x, b.bbuf, b.piv, b.descs, nmat, S, st)) != hipSuccess)
+      return e;
+    ++nl;
+    if (next) {
+      if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offN[S],
+                             nmat * b.cntN[S], S, st)) != hipSuccess)
+        return e;
+      ++nl;
+      if ((e = hipEventRecord(ax.evN, st)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(ax.st2, ax.evN, 0)) != hipSuccess) return e;
+      if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, S + 1, b.status,
+                            ax.st2)) != hipSuccess)
+        return e;
+      ++nl;
+      if ((e = hipEventRecord(ax.evP, ax.st2)) != hipSuccess) return e;
+    }
+    if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offB[S],
+                           nmat * b.cntB[S], S, st)) != hipSuccess)
+      return e;
+    ++nl;
+    if (next && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess) return e;
   }
   if (ev_steps && (e = hipEventRecord(ev_steps[1], st)) != hipSuccess) return e;
+  if (launches) *launches += nl;
   return hipSuccess;
 }
 
@@ -330,6 +369,7 @@ struct fk_ctx {
   Batch<double> b64;           // lattice batch (complex128)
   Batch<float> b32;            // lattice batch (complex64), lazily
   Batch<double> imp;           // impurity inversions (2 slots)
+  Aux aux;                     // look-ahead stream and events
   size_t batch_bytes = 0;
   int want_batch = 0;
 
@@ -365,7 +405,7 @@ fk_status set_err(fk_ctx* c, fk_status s, const char* fmt, ...) {
   } while (0)
 
 template <typename T> int batch_cap_for(fk_ctx* c) {
-  const size_t per = sizeof(cplx<T>) * (size_t)c->ci.n_c * c->ci.n_c +
+  const size_t per = sizeof(cplx<T>) * ((size_t)c->ci.n_c + kNBO) * c->ci.n_c +
                      2 * sizeof(int) * (size_t)c->ci.n_c;
   size_t cap = c->batch_bytes / per;
   if (c->want_batch > 0) cap = (size_t)c->want_batch;
@@ -443,7 +483,7 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
     HIPCHK(c, launch_build<T>(c->d_sigt, c->tab, k0, nmat, b.x, b.stride, b.ld,
                               n, c->st));
     HIPCHK(c, hipEventRecord(c->ev[1], c->st));
-    HIPCHK(c, batch_invert<T>(b, nmat, c->st, &launches, &c->ev[6]));
+    HIPCHK(c, batch_invert<T>(b, nmat, c->st, c->aux, &launches, &c->ev[6]));
     HIPCHK(c, hipEventRecord(c->ev[2], c->st));
     HIPCHK(c, launch_reduce<T>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                c->d_rho + k0, nmat, n, c->d_gloc, k0 > 0 ? 1 : 0,
@@ -481,7 +521,7 @@ fk_status impurity(fk_ctx* c, double* dsig) {
   HIPCHK(c, hipEventRecord(c->ev[4], c->st));
   // g0inv = (G_loc W)^-1 + Sigma W
   HIPCHK(c, launch_right_weight(c->d_gloc, c->d_w, b.x, b.ld, n, c->st));
-  HIPCHK(c, batch_invert<double>(b, 1, c->st, &launches));
+  HIPCHK(c, batch_invert<double>(b, 1, c->st, c->aux, &launches));
   if ((s = check_status(c, b.status, 1, 0, "inverse of G_loc W")) != FK_OK) return s;
   HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                   c->d_coef, 1, n, c->d_g0inv, 0, c->st));
@@ -497,13 +537,13 @@ fk_status impurity(fk_ctx* c, double* dsig) {
   }
   HIPCHK(c, launch_shifted_pair(c->d_g0inv, d0, d1, b.x, b.x + b.stride, b.ld, n,
                                 c->st));
-  HIPCHK(c, batch_invert<double>(b, 2, c->st, &launches));
+  HIPCHK(c, batch_invert<double>(b, 2, c->st, c->aux, &launches));
   if ((s = check_status(c, b.status, 2, 0, "impurity resolvents")) != FK_OK) return s;
   HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                   c->d_coef + 1, 2, n, c->d_tmp, 0, c->st));
   HIPCHK(c, hipMemcpyAsync(b.x, c->d_tmp, sizeof(c64) * (size_t)n * n,
                            hipMemcpyDeviceToDevice, c->st));
-  HIPCHK(c, batch_invert<double>(b, 1, c->st, &launches));
+  HIPCHK(c, batch_invert<double>(b, 1, c->st, c->aux, &launches));
   if ((s = check_status(c, b.status, 1, 0, "inverse of G_imp")) != FK_OK) return s;
   HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                   c->d_coef, 1, n, c->d_tmp, 0, c->st));
@@ -557,6 +597,9 @@ void free_ctx(fk_ctx* c) {
   batch_free(c->imp);
   for (hipEvent_t& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->aux.evN) (void)hipEventDestroy(c->aux.evN);
+  if (c->aux.evP) (void)hipEventDestroy(c->aux.evP);
+  if (c->aux.st2) (void)hipStreamDestroy(c->aux.st2);
   if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
 }
 
@@ -672,6 +715,9 @@ extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
   if (e == hipSuccess) e = hipMalloc(&c->d_key, sizeof(unsigned long long));
   for (hipEvent_t& ev : c->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux.st2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->aux.evN, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->aux.evP, hipEventDisableTiming);
   if (e != hipSuccess) {
     const fk_status s = (e == hipErrorOutOfMemory) ? FK_ENOMEM : FK_EDEVICE;
     free_ctx(c);

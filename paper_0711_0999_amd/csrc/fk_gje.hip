@@ -1,23 +1,25 @@
 // Batched blocked in-place Gauss-Jordan inversion with partial pivoting, for
 // gfx950.  This is the hot loop of the lattice step: every (eps, ebar) point
 // needs the inverse of the dense complex matrix G0_k^-1 - W Sigma W (the
-// "matrix inversion" of the paper's integrand, Sec. II, eq. g_loc).
+// "matrix inversion" of the integrand of eq. g_loc, Sec. II).
 //
-// Algorithm (one step per kNB-column panel, all matrices of the batch in one
-// launch):
-//   * The panel columns of step s were factored by the previous launch: for
-//     each panel column c a pivot row piv[c] was chosen among the rows not yet
-//     pivoted (largest |re|+|im|), and the panel now holds the transformed
-//     identity columns M = E[:, P] of the elementary Gauss-Jordan transforms.
-//   * Every other column stripe (kNB columns, all rows) is owned by one
-//     workgroup, which applies the deferred rank-kNB update
-//         C <- mask_P(C) + M * B,   B = old values of the pivot rows P,
-//     (mask_P zeroes the pivot rows) on the matrix cores (complex product as
-//     four real MFMA products), row tile by row tile.
-//   * The workgroup that owns the stripe of step s+1 then factors it as the
-//     next panel (look-ahead): kIB columns at a time in registers with a
-//     workgroup-wide pivot search, the rest of the panel updated through LDS.
-// Rows are never swapped: with r = piv and rinv = rowcol, the inverse is
+// Outer step S handles the block of kNBO = 128 columns starting at J0 = S*kNBO:
+//   panel   (one 512-thread workgroup per matrix) eliminates the block's two
+//           64-column inner panels in turn.  For each column the pivot is the
+//           largest |re|+|im| among the rows not yet pivoted; kIB columns are
+//           eliminated in registers at a time, the rest of the inner panel is
+//           updated in coalesced passes, and the other inner panel receives
+//           the rank-64 transform on the matrix cores.  Afterwards the block
+//           holds the transformed identity columns M = E[:, P] of all
+//           elementary Gauss-Jordan transforms of the step.
+//   gather  copies the pivot rows P of the step (their values before the
+//           step) into a side buffer B.
+//   update  every other column tile: C <- mask_P(C) + M B (K = 128), a batched
+//           complex GEMM on the matrix cores (four real products per complex
+//           one), double-buffered K chunks in LDS, two workgroups per CU.
+// The host runs the update of the next block's columns first and factors that
+// block on a second stream while the big update of the current step runs.
+// Rows are never swapped: with r = piv and rinv = rowcol the inverse is
 // inv(A)[a][b] = X[r[a]][rinv[b]], which the reduction kernels read directly.
 #include "fk_internal.h"
 
@@ -50,159 +52,6 @@ template <typename T> __device__ inline T big_value();
 template <> __device__ inline double big_value<double>() { return DBL_MAX; }
 template <> __device__ inline float big_value<float>() { return FLT_MAX; }
 
-constexpr int kPitch = kNB + 1;            // padded LDS row (complex elements)
-constexpr int kRPT = kMaxN / kThreads;     // panel rows per thread
-static_assert(kMaxN % kThreads == 0, "kMaxN must be a multiple of kThreads");
-
-// ---------------------------------------------------------------- update ---
-// C <- mask(C) + M B on the stripe [c0, c0+cw) of one matrix, all rows.
-template <typename T>
-__device__ void update_stripe(cplx<T>* __restrict__ x, int ld, int n,
-                              const int* __restrict__ piv,
-                              const int* __restrict__ rowcol, int step, int q,
-                              unsigned char* smem) {
-  typedef typename Mfma<T>::v4 v4;
-  cplx<T>* Bs = reinterpret_cast<cplx<T>*>(smem);   // [kNB][kPitch]
-  cplx<T>* Ms = Bs + kNB * kPitch;                   // [kTM][kPitch]
-  const int tid = threadIdx.x;
-  const int j0 = step * kNB;
-  const int w = min(kNB, n - j0);
-  const int c0 = q * kNB;
-  const int cw = min(kNB, n - c0);
-
-  // old pivot rows of this stripe; zero-padded to kNB x kNB.  All loads use
-  // clamped (in-range) addresses and are masked afterwards, so that they are
-  // issued together instead of one branch-guarded round trip at a time.
-  {
-    int pr[kNB * kNB / kThreads];
-#pragma unroll
-    for (int t = 0; t < kNB * kNB / kThreads; ++t) {
-      const int l = (tid + t * kThreads) / kNB;
-      pr[t] = piv[j0 + min(l, w - 1)];
-    }
-    cplx<T> bv[kNB * kNB / kThreads];
-#pragma unroll
-    for (int t = 0; t < kNB * kNB / kThreads; ++t) {
-      const int e = tid + t * kThreads;
-      const int c = e % kNB;
-      bv[t] = x[(size_t)pr[t] * ld + c0 + min(c, cw - 1)];
-    }
-#pragma unroll
-    for (int t = 0; t < kNB * kNB / kThreads; ++t) {
-      const int e = tid + t * kThreads;
-      const int l = e / kNB, c = e % kNB;
-      cplx<T> v = bv[t];
-      if (!(l < w && c < cw)) v.re = v.im = T(0);
-      Bs[l * kPitch + c] = v;
-    }
-  }
-
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int li = lane & 15, lk = lane >> 4;
-
-  for (int r0 = 0; r0 < n; r0 += kTM) {
-    __syncthreads();  // Bs written / previous Ms consumed
-    constexpr int kML = kTM * kNB / kThreads;
-    cplx<T> mv[kML];
-#pragma unroll
-    for (int t = 0; t < kML; ++t) {
-      const int e = tid + t * kThreads;
-      const int i = e / kNB, l = e % kNB;
-      mv[t] = x[(size_t)min(r0 + i, n - 1) * ld + j0 + min(l, w - 1)];
-    }
-    int rcv[2][4];
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
-        rcv[ii][v] = rowcol[min(row, n - 1)];
-      }
-    cplx<T> cv[2][2][4];
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
-          const int col = 32 * wc + 16 * jj + li;
-          cv[ii][jj][v] = x[(size_t)min(row, n - 1) * ld + c0 + min(col, cw - 1)];
-        }
-#pragma unroll
-    for (int t = 0; t < kML; ++t) {
-      const int e = tid + t * kThreads;
-      const int i = e / kNB, l = e % kNB;
-      cplx<T> v = mv[t];
-      if (!(r0 + i < n && l < w)) v.re = v.im = T(0);
-      Ms[i * kPitch + l] = v;
-    }
-    v4 cr[2][2], ci[2][2];
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
-          const int col = 32 * wc + 16 * jj + li;
-          const int rc = rcv[ii][v];
-          const bool keep = row < n && col < cw && !(rc >= j0 && rc < j0 + w);
-          cr[ii][jj][v] = keep ? cv[ii][jj][v].re : T(0);
-          ci[ii][jj][v] = keep ? cv[ii][jj][v].im : T(0);
-        }
-    __syncthreads();  // Ms ready
-#pragma unroll 4
-    for (int k = 0; k < kNB; k += 4) {
-      T ar[2], ai[2], an[2], br[2], bi[2];
-#pragma unroll
-      for (int ii = 0; ii < 2; ++ii) {
-        const cplx<T> a = Ms[(32 * wr + 16 * ii + li) * kPitch + k + lk];
-        ar[ii] = a.re;
-        ai[ii] = a.im;
-        an[ii] = -a.im;
-      }
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj) {
-        const cplx<T> b = Bs[(k + lk) * kPitch + 32 * wc + 16 * jj + li];
-        br[jj] = b.re;
-        bi[jj] = b.im;
-      }
-#pragma unroll
-      for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          cr[ii][jj] = Mfma<T>::run(ar[ii], br[jj], cr[ii][jj]);
-          cr[ii][jj] = Mfma<T>::run(an[ii], bi[jj], cr[ii][jj]);
-          ci[ii][jj] = Mfma<T>::run(ar[ii], bi[jj], ci[ii][jj]);
-          ci[ii][jj] = Mfma<T>::run(ai[ii], br[jj], ci[ii][jj]);
-        }
-    }
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
-          const int col = 32 * wc + 16 * jj + li;
-          if (row < n && col < cw) {
-            cplx<T> c;
-            c.re = cr[ii][jj][v];
-            c.im = ci[ii][jj][v];
-            x[(size_t)row * ld + c0 + col] = c;
-          }
-        }
-  }
-}
-
-// ----------------------------------------------------------------- panel ---
-template <typename T>
-__device__ inline void cmul_sub(cplx<T>& acc, const cplx<T>& a, const cplx<T>& b) {
-  acc.re -= a.re * b.re - a.im * b.im;
-  acc.im -= a.re * b.im + a.im * b.re;
-}
 template <typename T>
 __device__ inline cplx<T> cmul(const cplx<T>& a, const cplx<T>& b) {
   cplx<T> r;
@@ -210,44 +59,166 @@ __device__ inline cplx<T> cmul(const cplx<T>& a, const cplx<T>& b) {
   r.im = a.re * b.im + a.im * b.re;
   return r;
 }
-
-// Factor the stripe q (columns [c0, c0+cw), all rows) as a Gauss-Jordan panel.
 template <typename T>
-__device__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
+__device__ inline void cfma(cplx<T>& acc, const cplx<T>& a, const cplx<T>& b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+
+constexpr int kPW = kPanelThreads / 64;          // waves of the panel kernel
+constexpr int kRPT = kMaxN / kPanelThreads;      // panel rows per thread
+constexpr int kPitch = kNB + 1;                  // padded LDS row (elements)
+static_assert(kMaxN % kPanelThreads == 0, "kMaxN");
+static_assert(kNBO == 2 * kNB && kTile == kNB, "block sizes");
+
+// ------------------------------------------------------ panel: inner update
+// C <- mask(C) + M B on the 64-column stripe q of one matrix, with M the
+// columns of inner panel p (already eliminated) and B the old values of p's
+// pivot rows in stripe q (read before any write: this workgroup owns q).
+// The kPW waves form (kPW/4) x 4 blocks of (16 kRB) x 16 over each 64 x 64 tile.
+constexpr int kRB = kTile / (16 * (kPW / 4));   // 16-row blocks per wave
+static_assert(kPW % 4 == 0 && kRB >= 1, "panel waves");
+template <typename T>
+__device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, int n,
+                             const int* __restrict__ piv,
+                             const int* __restrict__ rowcol, int p, int q,
+                             unsigned char* smem) {
+  typedef typename Mfma<T>::v4 v4;
+  cplx<T>* Bs = reinterpret_cast<cplx<T>*>(smem);   // [kNB][kPitch]
+  cplx<T>* Ms = Bs + kNB * kPitch;                   // [kTile][kPitch]
+  const int tid = threadIdx.x;
+  const int j0 = p * kNB, w = min(kNB, n - j0);
+  const int c0 = q * kNB, cw = min(kNB, n - c0);
+  constexpr int kL = kNB * kNB / kPanelThreads;     // elements per thread
+  {
+    int pr[kL];
+    cplx<T> bv[kL];
+#pragma unroll
+    for (int t = 0; t < kL; ++t) {
+      const int l = (tid + t * kPanelThreads) / kNB;
+      pr[t] = piv[j0 + min(l, w - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < kL; ++t) {
+      const int c = (tid + t * kPanelThreads) % kNB;
+      bv[t] = x[(size_t)pr[t] * ld + c0 + min(c, cw - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < kL; ++t) {
+      const int e = tid + t * kPanelThreads;
+      const int l = e / kNB, c = e % kNB;
+      cplx<T> v = bv[t];
+      if (!(l < w && c < cw)) v.re = v.im = T(0);
+      Bs[l * kPitch + c] = v;
+    }
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int li = lane & 15, lk = lane >> 4;
+  const int col = 16 * wc + li;
+  for (int r0 = 0; r0 < n; r0 += kTile) {
+    __syncthreads();
+    cplx<T> mv[kL];
+#pragma unroll
+    for (int t = 0; t < kL; ++t) {
+      const int e = tid + t * kPanelThreads;
+      const int i = e / kNB, l = e % kNB;
+      mv[t] = x[(size_t)min(r0 + i, n - 1) * ld + j0 + min(l, w - 1)];
+    }
+    int rcv[kRB][4];
+    cplx<T> cv[kRB][4];
+#pragma unroll
+    for (int ii = 0; ii < kRB; ++ii)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        rcv[ii][v] = rowcol[min(row, n - 1)];
+        cv[ii][v] = x[(size_t)min(row, n - 1) * ld + c0 + min(col, cw - 1)];
+      }
+#pragma unroll
+    for (int t = 0; t < kL; ++t) {
+      const int e = tid + t * kPanelThreads;
+      const int i = e / kNB, l = e % kNB;
+      cplx<T> v = mv[t];
+      if (!(r0 + i < n && l < w)) v.re = v.im = T(0);
+      Ms[i * kPitch + l] = v;
+    }
+    v4 cr[kRB], ci[kRB];
+#pragma unroll
+    for (int ii = 0; ii < kRB; ++ii)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        const bool keep = row < n && col < cw &&
+                          !(rcv[ii][v] >= j0 && rcv[ii][v] < j0 + w);
+        cr[ii][v] = keep ? cv[ii][v].re : T(0);
+        ci[ii][v] = keep ? cv[ii][v].im : T(0);
+      }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kNB; k += 4) {
+      const cplx<T> b = Bs[(k + lk) * kPitch + col];
+#pragma unroll
+      for (int ii = 0; ii < kRB; ++ii) {
+        const cplx<T> a = Ms[(16 * (kRB * wr + ii) + li) * kPitch + k + lk];
+        cr[ii] = Mfma<T>::run(a.re, b.re, cr[ii]);
+        ci[ii] = Mfma<T>::run(a.re, b.im, ci[ii]);
+        cr[ii] = Mfma<T>::run(-a.im, b.im, cr[ii]);
+        ci[ii] = Mfma<T>::run(a.im, b.re, ci[ii]);
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < kRB; ++ii)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        if (row < n && col < cw) {
+          cplx<T> c;
+          c.re = cr[ii][v];
+          c.im = ci[ii][v];
+          x[(size_t)row * ld + c0 + col] = c;
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------- panel: factorization
+// Eliminate the columns of inner panel q (all rows) with partial pivoting.
+template <typename T>
+__device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
                              int* __restrict__ piv, int* __restrict__ rowcol,
                              int q, int* __restrict__ status,
                              unsigned char* smem) {
-  cplx<T>* Mi = reinterpret_cast<cplx<T>*>(smem);   // [kMaxN][kIB]
-  cplx<T>* Bo = Mi + kMaxN * kIB;                    // [kIB][kNB]
+  cplx<T>* Bo = reinterpret_cast<cplx<T>*>(smem);   // [kIB][kNB]
   cplx<T>* prow = Bo + kIB * kNB;                    // [kIB]
-  T* redv = reinterpret_cast<T*>(prow + kIB);        // [4]
-  int* redi = reinterpret_cast<int*>(redv + 4);      // [4]
-  int* pvt = redi + 4;                               // [kIB]
+  T* redv = reinterpret_cast<T*>(prow + kIB);        // [kPW]
+  int* redi = reinterpret_cast<int*>(redv + kPW);    // [kPW]
+  int* pvt = redi + kPW;                             // [kIB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = q * kNB;
-  const int cw = min(kNB, n - c0);
+  const int c0 = q * kNB, cw = min(kNB, n - c0);
   const T inf_key = big_value<T>();
 
   bool pvd[kRPT];
 #pragma unroll
   for (int i = 0; i < kRPT; ++i) {
-    const int r = tid + i * kThreads;
-    pvd[i] = (r < n) ? (rowcol[r] >= 0) : true;
+    const int r = tid + i * kPanelThreads;
+    pvd[i] = (r < n) ? (rowcol[min(r, n - 1)] >= 0) : true;
   }
+  const int ngroups = (cw + kIB - 1) / kIB;
 
   for (int b0 = 0; b0 < cw; b0 += kIB) {
     const int iw = min(kIB, cw - b0);
     cplx<T> v[kRPT][kIB];
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
-      const int r = min(tid + i * kThreads, n - 1);
+      const int r = min(tid + i * kPanelThreads, n - 1);
 #pragma unroll
       for (int l = 0; l < kIB; ++l)
         v[i][l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
     }
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
-      const int r = tid + i * kThreads;
+      const int r = tid + i * kPanelThreads;
 #pragma unroll
       for (int l = 0; l < kIB; ++l)
         if (!(r < n && l < iw)) v[i][l].re = v[i][l].im = T(0);
@@ -260,7 +231,7 @@ __device__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
       int bidx = INT_MAX;
 #pragma unroll
       for (int i = 0; i < kRPT; ++i) {
-        const int r = tid + i * kThreads;
+        const int r = tid + i * kPanelThreads;
         if (r < n && !pvd[i]) {
           T a = fabs(v[i][l].re) + fabs(v[i][l].im);
           if (!(a <= inf_key)) a = inf_key;  // NaN / Inf win and get flagged
@@ -287,7 +258,7 @@ __device__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
       best = redv[0];
       bidx = redi[0];
 #pragma unroll
-      for (int wv = 1; wv < kThreads / 64; ++wv) {
+      for (int wv = 1; wv < kPW; ++wv) {
         const T ob = redv[wv];
         const int oi = redi[wv];
         if (ob > best || (ob == best && oi < bidx)) {
@@ -295,12 +266,12 @@ __device__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
           bidx = oi;
         }
       }
-      const int p = bidx;  // always a valid unpivoted row: fewer than n pivots so far
+      const int p = bidx;  // a valid unpivoted row: fewer than n pivots so far
       const int col = c0 + b0 + l;
       if (tid == 0 && (best == T(0) || best == inf_key))
         atomicCAS(status, 0, best == T(0) ? (1 + col) : -(1 + col));
-      if ((p % kThreads) == tid) {
-        const int i = p / kThreads;
+      if ((p % kPanelThreads) == tid) {
+        const int i = p / kPanelThreads;
 #pragma unroll
         for (int ii = 0; ii < kRPT; ++ii)
           if (ii == i) {
@@ -325,154 +296,365 @@ __device__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
       ps[l] = inv;
 #pragma unroll
       for (int i = 0; i < kRPT; ++i) {
-        const int r = tid + i * kThreads;
-        if (r < n) {
-          if (r == p) {
+        const int r = tid + i * kPanelThreads;
+        if (r == p) {
 #pragma unroll
-            for (int l2 = 0; l2 < kIB; ++l2) v[i][l2] = ps[l2];
-          } else {
-            const cplx<T> m = v[i][l];
+          for (int l2 = 0; l2 < kIB; ++l2) v[i][l2] = ps[l2];
+        } else {
+          const cplx<T> m = v[i][l];
 #pragma unroll
-            for (int l2 = 0; l2 < kIB; ++l2)
-              if (l2 != l) cmul_sub(v[i][l2], m, ps[l2]);
-            cplx<T> nm = cmul(m, inv);
-            nm.re = -nm.re;
-            nm.im = -nm.im;
-            v[i][l] = nm;
-          }
+          for (int l2 = 0; l2 < kIB; ++l2)
+            if (l2 != l) {
+              v[i][l2].re -= m.re * ps[l2].re - m.im * ps[l2].im;
+              v[i][l2].im -= m.re * ps[l2].im + m.im * ps[l2].re;
+            }
+          const cplx<T> nm = cmul(m, inv);
+          v[i][l].re = -nm.re;
+          v[i][l].im = -nm.im;
         }
       }
       __syncthreads();  // redv / prow reused by the next column
     }
-    // ---- inner block done: write it back and keep it in LDS
+    // ---- write the eliminated block back; old pivot rows of the other columns
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
-      const int r = tid + i * kThreads;
+      const int r = tid + i * kPanelThreads;
       if (r < n) {
 #pragma unroll
-        for (int l = 0; l < kIB; ++l) {
+        for (int l = 0; l < kIB; ++l)
           if (l < iw) x[(size_t)r * ld + c0 + b0 + l] = v[i][l];
-          Mi[r * kIB + l] = v[i][l];  // zero beyond iw
-        }
       }
     }
-    // old values of this block's pivot rows in the other panel columns
-    for (int e = tid; e < kIB * kNB; e += kThreads) {
-      const int l = e / kNB, c = e - (e / kNB) * kNB;
-      cplx<T> t = {T(0), T(0)};
-      if (l < iw && c < cw && (c < b0 || c >= b0 + iw))
-        t = x[(size_t)pvt[l] * ld + c0 + c];
+    for (int e = tid; e < kIB * kNB; e += kPanelThreads) {
+      const int l = e / kNB, c = e % kNB;
+      const bool ok = l < iw && c < cw && (c < b0 || c >= b0 + iw);
+      cplx<T> t = x[(size_t)pvt[min(l, iw - 1)] * ld + c0 + min(c, cw - 1)];
+      if (!ok) t.re = t.im = T(0);
       Bo[e] = t;
     }
     __syncthreads();
-    // rank-iw update of the other panel columns (row-major, coalesced); the
-    // loads of kBat elements are issued before any of them is stored.
-    constexpr int kBat = 8;
-    const int total = n * cw;
+    // ---- rank-iw update of the other column groups of the panel.  Work unit:
+    // one row and one group of kIB columns; its 2 kIB loads go out together.
+    const int og = ngroups - 1;
+    const int cur = b0 / kIB;
+    const int units = n * og;
     int pv0[kIB];
 #pragma unroll
     for (int l = 0; l < kIB; ++l) pv0[l] = (l < iw) ? pvt[l] : -1;
-    for (int e0 = tid; e0 < total; e0 += kThreads * kBat) {
-      cplx<T> old[kBat];
+    for (int u = tid; u < units; u += kPanelThreads) {
+      const int r = u / og;
+      int g = u - r * og;
+      g += (g >= cur) ? 1 : 0;
+      const int cg = g * kIB, gw = min(kIB, cw - cg);
+      cplx<T> mm[kIB], od[kIB];
 #pragma unroll
-      for (int b = 0; b < kBat; ++b) {
-        const int e = min(e0 + b * kThreads, total - 1);
-        const int r = e / cw, c = e - (e / cw) * cw;
-        old[b] = x[(size_t)r * ld + c0 + c];
-      }
+      for (int l = 0; l < kIB; ++l)
+        mm[l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
 #pragma unroll
-      for (int b = 0; b < kBat; ++b) {
-        const int e = e0 + b * kThreads;
-        if (e >= total) break;
-        const int r = e / cw, c = e - (e / cw) * cw;
-        if (c >= b0 && c < b0 + iw) continue;
-        bool isp = false;
+      for (int cc = 0; cc < kIB; ++cc)
+        od[cc] = x[(size_t)r * ld + c0 + cg + min(cc, gw - 1)];
+      bool isp = false;
 #pragma unroll
-        for (int l = 0; l < kIB; ++l) isp |= (pv0[l] == r);
-        cplx<T> acc = old[b];
+      for (int l = 0; l < kIB; ++l) isp |= (pv0[l] == r);
+#pragma unroll
+      for (int cc = 0; cc < kIB; ++cc) {
+        cplx<T> acc = od[cc];
         if (isp) acc.re = acc.im = T(0);
 #pragma unroll
-        for (int l = 0; l < kIB; ++l) {
-          const cplx<T> mm = Mi[r * kIB + l];
-          const cplx<T> bb = Bo[l * kNB + c];
-          acc.re += mm.re * bb.re - mm.im * bb.im;
-          acc.im += mm.re * bb.im + mm.im * bb.re;
-        }
-        x[(size_t)r * ld + c0 + c] = acc;
+        for (int l = 0; l < kIB; ++l)
+          if (l < iw) cfma(acc, mm[l], Bo[l * kNB + cg + cc]);
+        if (cc < gw) x[(size_t)r * ld + c0 + cg + cc] = acc;
       }
     }
     __syncthreads();
   }
 }
 
-// ---------------------------------------------------------------- kernel ---
-// Work items are split into 8 contiguous chunks, one per XCD (workgroups are
-// dispatched round-robin over the 8 XCDs), so the stripes of one matrix share
-// that XCD's L2 when they read the panel.
 template <typename T>
-__global__ __launch_bounds__(kThreads, 1) void gje_step_kernel(
+__global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
     cplx<T>* __restrict__ xbuf, int* __restrict__ pivbuf,
-    int* __restrict__ rowcolbuf, const MatDesc* __restrict__ descs,
-    const WorkItem* __restrict__ items, int nitems, int step,
+    int* __restrict__ rowcolbuf, const MatDesc* __restrict__ descs, int S,
     int* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const MatDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  if (S * kNBO >= n) return;
+  cplx<T>* x = xbuf + d.xoff;
+  int* piv = pivbuf + d.ioff;
+  int* rowcol = rowcolbuf + d.ioff;
+  int* st = status + d.status_idx;
+  const int p0 = 2 * S, p1 = 2 * S + 1;
+  factor_panel<T>(x, d.ld, n, piv, rowcol, p0, st, smem);
+  if (p1 * kNB < n) {
+    __syncthreads();
+    inner_update<T>(x, d.ld, n, piv, rowcol, p0, p1, smem);
+    __syncthreads();
+    factor_panel<T>(x, d.ld, n, piv, rowcol, p1, st, smem);
+    __syncthreads();
+    inner_update<T>(x, d.ld, n, piv, rowcol, p1, p0, smem);
+  }
+}
+
+// ------------------------------------------------------------------ gather
+template <typename T>
+__global__ void k_gather(const cplx<T>* __restrict__ xbuf,
+                         cplx<T>* __restrict__ bbuf,
+                         const int* __restrict__ pivbuf,
+                         const MatDesc* __restrict__ descs, int S) {
+  const MatDesc d = descs[blockIdx.y];
+  const int l = blockIdx.x;
+  const int J0 = S * kNBO;
+  if (J0 >= d.n || l >= min(kNBO, d.n - J0)) return;
+  const int p = pivbuf[d.ioff + J0 + l];
+  const cplx<T>* src = xbuf + d.xoff + (size_t)p * d.ld;
+  cplx<T>* dst = bbuf + d.boff + (size_t)l * d.ld;
+  for (int c = threadIdx.x; c < d.n; c += blockDim.x) dst[c] = src[c];
+}
+
+// ------------------------------------------------------------------ update
+// C <- mask_P(C) + M B for the listed 64 x 64 tiles.  Four waves as 2 x 2
+// blocks of 32 x 32; K in chunks of kKC, double-buffered through LDS with the
+// next chunk's global loads in flight during the current chunk's MFMAs.
+template <typename T>
+__global__ __launch_bounds__(kGemmThreads, 2) void k_update(
+    cplx<T>* __restrict__ xbuf, const cplx<T>* __restrict__ bbuf,
+    const int* __restrict__ rowcolbuf, const MatDesc* __restrict__ descs,
+    const TileItem* __restrict__ items, int nitems, int S) {
+  typedef typename Mfma<T>::v4 v4;
+  constexpr int AP = kKC + 1, BP = kTile + 1;
+  __shared__ cplx<T> As[2][kTile * AP];
+  __shared__ cplx<T> Bsh[2][kKC * BP];
+  constexpr int kLA = kTile * kKC / kGemmThreads;   // chunk loads per thread
+  constexpr int kLB = kKC * kTile / kGemmThreads;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int per = gridDim.x >> 3;
   const int chunk = (nitems + 7) >> 3;
-  const int lo = xcd * chunk;
-  const int hi = min(nitems, lo + chunk);
+  const int lo = xcd * chunk, hi = min(nitems, lo + chunk);
+
   for (int it = lo + slot; it < hi; it += per) {
-    const WorkItem wi = items[it];
-    const MatDesc d = descs[wi.mat];
-    cplx<T>* x = xbuf + d.xoff;
-    int* piv = pivbuf + d.ioff;
-    int* rowcol = rowcolbuf + d.ioff;
-    if (step >= 0 && wi.stripe != step)
-      update_stripe<T>(x, d.ld, d.n, piv, rowcol, step, wi.stripe, smem);
-    if (wi.stripe == step + 1 && wi.stripe * kNB < d.n) {
-      __syncthreads();
-      factor_panel<T>(x, d.ld, d.n, piv, rowcol, wi.stripe,
-                      status + d.status_idx, smem);
+    const TileItem ti = items[it];
+    const MatDesc d = descs[ti.mat];
+    const int n = d.n, ld = d.ld;
+    const int J0 = S * kNBO, wO = min(kNBO, n - J0);
+    const int nch = (wO + kKC - 1) / kKC;
+    const int r0 = ti.tr * kTile, c0 = ti.tc * kTile;
+    cplx<T>* xm = xbuf + d.xoff;
+    const cplx<T>* bm = bbuf + d.boff;
+    const int* rowcol = rowcolbuf + d.ioff;
+
+    // C tile and pivot-row mask
+    int rcv[2][4];
+    cplx<T> cv[2][2][4];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        rcv[ii][v] = rowcol[min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1)];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1);
+          const int col = min(c0 + 32 * wc + 16 * jj + li, n - 1);
+          cv[ii][jj][v] = xm[(size_t)row * ld + col];
+        }
+    // chunk 0
+    cplx<T> pa[kLA], pb[kLB];
+#pragma unroll
+    for (int t = 0; t < kLA; ++t) {
+      const int e = tid + t * kGemmThreads;
+      const int i = e / kKC, k = e % kKC;
+      pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(k, wO - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+      const int e = tid + t * kGemmThreads;
+      const int k = e / kTile, c = e % kTile;
+      pb[t] = bm[(size_t)min(k, wO - 1) * ld + min(c0 + c, n - 1)];
+    }
+    v4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
+          const int col = c0 + 32 * wc + 16 * jj + li;
+          const int rc = rcv[ii][v];
+          const bool keep = row < n && col < n && !(rc >= J0 && rc < J0 + wO);
+          cr[ii][jj][v] = keep ? cv[ii][jj][v].re : T(0);
+          ci[ii][jj][v] = keep ? cv[ii][jj][v].im : T(0);
+        }
+#pragma unroll
+    for (int t = 0; t < kLA; ++t) {
+      const int e = tid + t * kGemmThreads;
+      const int i = e / kKC, k = e % kKC;
+      cplx<T> v = pa[t];
+      if (!(r0 + i < n && k < wO)) v.re = v.im = T(0);
+      As[0][i * AP + k] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+      const int e = tid + t * kGemmThreads;
+      const int k = e / kTile, c = e % kTile;
+      cplx<T> v = pb[t];
+      if (!(k < wO && c0 + c < n)) v.re = v.im = T(0);
+      Bsh[0][k * BP + c] = v;
     }
     __syncthreads();
+
+    for (int kc = 0; kc < nch; ++kc) {
+      const int buf = kc & 1;
+      const bool more = kc + 1 < nch;
+      const int kb = (kc + 1) * kKC;
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < kLA; ++t) {
+          const int e = tid + t * kGemmThreads;
+          const int i = e / kKC, k = e % kKC;
+          pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(kb + k, wO - 1)];
+        }
+#pragma unroll
+        for (int t = 0; t < kLB; ++t) {
+          const int e = tid + t * kGemmThreads;
+          const int k = e / kTile, c = e % kTile;
+          pb[t] = bm[(size_t)min(kb + k, wO - 1) * ld + min(c0 + c, n - 1)];
+        }
+      }
+      const cplx<T>* as = As[buf];
+      const cplx<T>* bs = Bsh[buf];
+#pragma unroll
+      for (int k = 0; k < kKC; k += 4) {
+        T ar[2], ai[2], an[2], br[2], bi[2];
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii) {
+          const cplx<T> a = as[(32 * wr + 16 * ii + li) * AP + k + lk];
+          ar[ii] = a.re;
+          ai[ii] = a.im;
+          an[ii] = -a.im;
+        }
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const cplx<T> b = bs[(k + lk) * BP + 32 * wc + 16 * jj + li];
+          br[jj] = b.re;
+          bi[jj] = b.im;
+        }
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            cr[ii][jj] = Mfma<T>::run(ar[ii], br[jj], cr[ii][jj]);
+            ci[ii][jj] = Mfma<T>::run(ar[ii], bi[jj], ci[ii][jj]);
+          }
+#pragma unroll
+        for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            cr[ii][jj] = Mfma<T>::run(an[ii], bi[jj], cr[ii][jj]);
+            ci[ii][jj] = Mfma<T>::run(ai[ii], br[jj], ci[ii][jj]);
+          }
+      }
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < kLA; ++t) {
+          const int e = tid + t * kGemmThreads;
+          const int i = e / kKC, k = e % kKC;
+          cplx<T> v = pa[t];
+          if (!(r0 + i < n && kb + k < wO)) v.re = v.im = T(0);
+          As[buf ^ 1][i * AP + k] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < kLB; ++t) {
+          const int e = tid + t * kGemmThreads;
+          const int k = e / kTile, c = e % kTile;
+          cplx<T> v = pb[t];
+          if (!(kb + k < wO && c0 + c < n)) v.re = v.im = T(0);
+          Bsh[buf ^ 1][k * BP + c] = v;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
+          const int col = c0 + 32 * wc + 16 * jj + li;
+          if (row < n && col < n) {
+            cplx<T> c;
+            c.re = cr[ii][jj][v];
+            c.im = ci[ii][jj][v];
+            xm[(size_t)row * ld + col] = c;
+          }
+        }
   }
 }
 
-template <typename T> size_t gje_lds_bytes() {
-  const size_t upd = sizeof(cplx<T>) * (size_t)(kNB + kTM) * kPitch;
-  const size_t pan = sizeof(cplx<T>) * ((size_t)kMaxN * kIB + kIB * kNB + kIB) +
-                     4 * sizeof(T) + 4 * sizeof(int) + kIB * sizeof(int);
-  return upd > pan ? upd : pan;
+// --------------------------------------------------------------- launchers
+template <typename T> static size_t panel_lds_bytes() {
+  const size_t upd = sizeof(cplx<T>) * (size_t)(kNB + kTile) * kPitch;
+  const size_t fac = sizeof(cplx<T>) * (kIB * kNB + kIB) + kPW * sizeof(T) +
+                     kPW * sizeof(int) + kIB * sizeof(int);
+  return upd > fac ? upd : fac;
 }
 
 template <typename T>
-hipError_t gje_step(cplx<T>* xbuf, int* pivbuf, int* rowcolbuf,
-                    const MatDesc* descs, const WorkItem* items, int nitems,
-                    int step, int* status, int grid, hipStream_t st) {
+hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
+                     int nmat, int S, int* status, hipStream_t st) {
   static bool attr_set = false;
-  const size_t lds = gje_lds_bytes<T>();
+  const size_t lds = panel_lds_bytes<T>();
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&gje_step_kernel<T>),
+        reinterpret_cast<const void*>(&k_outer_panel<T>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (nitems <= 0) return hipSuccess;
-  if (grid <= 0 || (grid & 7)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gje_step_kernel<T>, dim3(grid), dim3(kThreads), lds, st,
-                     xbuf, pivbuf, rowcolbuf, descs, items, nitems, step,
-                     status);
+  if (nmat <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_outer_panel<T>, dim3(nmat), dim3(kPanelThreads), lds, st,
+                     x, piv, rowcol, d, S, status);
   return hipGetLastError();
 }
 
-template hipError_t gje_step<double>(c64*, int*, int*, const MatDesc*,
-                                     const WorkItem*, int, int, int*, int,
-                                     hipStream_t);
-template hipError_t gje_step<float>(c32*, int*, int*, const MatDesc*,
-                                    const WorkItem*, int, int, int*, int,
+template <typename T>
+hipError_t gje_gather(const cplx<T>* x, cplx<T>* bbuf, const int* piv,
+                      const MatDesc* d, int nmat, int S, hipStream_t st) {
+  if (nmat <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather<T>, dim3(kNBO, nmat), dim3(256), 0, st, x, bbuf,
+                     piv, d, S);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
+                      const MatDesc* d, const TileItem* items, int nitems,
+                      int S, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  const int grid = 8 * ((nitems + 7) / 8);
+  hipLaunchKernelGGL(k_update<T>, dim3(grid), dim3(kGemmThreads), 0, st, x,
+                     bbuf, rowcol, d, items, nitems, S);
+  return hipGetLastError();
+}
+
+#define FK_INST(T)                                                            \
+  template hipError_t gje_panel<T>(cplx<T>*, int*, int*, const MatDesc*, int, \
+                                   int, int*, hipStream_t);                   \
+  template hipError_t gje_gather<T>(const cplx<T>*, cplx<T>*, const int*,     \
+                                    const MatDesc*, int, int, hipStream_t);   \
+  template hipError_t gje_update<T>(cplx<T>*, const cplx<T>*, const int*,     \
+                                    const MatDesc*, const TileItem*, int, int, \
                                     hipStream_t);
-template size_t gje_lds_bytes<double>();
-template size_t gje_lds_bytes<float>();
+FK_INST(double)
+FK_INST(float)
 
 }  // namespace fk

@@ -11,38 +11,50 @@ template <typename T> struct alignas(2 * sizeof(T)) cplx { T re, im; };
 typedef cplx<double> c64;
 typedef cplx<float> c32;
 
-// One matrix of a batched Gauss-Jordan inversion.  x points at element (0,0)
-// of an n x n row-major matrix with leading dimension ld (elements); piv and
-// rowcol point at n ints each: piv[c] = row chosen as pivot for column c,
-// rowcol[r] = column whose pivot row is r (-1 while r is unpivoted).
+// One matrix of a batched Gauss-Jordan inversion.  x + xoff is element (0,0)
+// of an n x n row-major matrix with leading dimension ld (elements).
+// piv + ioff and rowcol + ioff hold n ints each: piv[c] = row chosen as pivot
+// for column c, rowcol[r] = column whose pivot row is r (-1 while unpivoted).
+// bbuf + boff holds kNBO rows of ld elements: the gathered old pivot rows of
+// the current outer step.
 struct MatDesc {
-  long long xoff;   // element offset of the matrix in the batch buffer
+  long long xoff;
+  long long boff;
   int n;
   int ld;
-  int ioff;         // int offset of piv / rowcol for this matrix
-  int status_idx;   // slot in the status array
+  int ioff;
+  int status_idx;
 };
 
-// Work item of one inversion step: (matrix, column stripe).
-struct WorkItem {
+// Tile of the trailing update: (matrix, row tile, column tile) of kTile.
+struct TileItem {
   int mat;
-  int stripe;
+  short tr;
+  short tc;
 };
 
-constexpr int kNB = 64;        // panel width = stripe width (columns)
-constexpr int kTM = 64;        // row tile of the trailing update
-constexpr int kIB = 4;         // inner panel block held in registers
-constexpr int kThreads = 256;  // workgroup size of the step kernel
-constexpr int kMaxN = 2304;    // largest matrix the step kernel supports
+constexpr int kNB = 64;          // inner panel width (columns)
+constexpr int kNBO = 128;        // outer block: two inner panels
+constexpr int kTile = 64;        // trailing-update tile (rows = cols)
+constexpr int kKC = 16;          // K chunk of the trailing update
+constexpr int kIB = 8;           // panel columns eliminated in registers at once
+constexpr int kPanelThreads = 512;
+constexpr int kGemmThreads = 256;
+constexpr int kMaxN = 2048;      // largest matrix the inversion supports
 
-// Launch one step of the blocked in-place Gauss-Jordan inversion for a batch.
-// step = -1 factors the first panel only.  items[0..nitems) on the device.
+// Outer step S of the blocked in-place Gauss-Jordan inversion, pieces:
+//   panel   one workgroup per matrix factors the outer block [S*kNBO, +kNBO)
+//   gather  copies the old pivot rows of outer step S into the side buffer
+//   update  C <- mask(C) + M B on the listed tiles (K = outer block width)
 template <typename T>
-hipError_t gje_step(cplx<T>* xbuf, int* pivbuf, int* rowcolbuf,
-                    const MatDesc* descs, const WorkItem* items, int nitems,
-                    int step, int* status, int grid, hipStream_t st);
-
-// Dynamic LDS bytes used by gje_step for element type T.
-template <typename T> size_t gje_lds_bytes();
+hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
+                     int nmat, int S, int* status, hipStream_t st);
+template <typename T>
+hipError_t gje_gather(const cplx<T>* x, cplx<T>* bbuf, const int* piv,
+                      const MatDesc* d, int nmat, int S, hipStream_t st);
+template <typename T>
+hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
+                      const MatDesc* d, const TileItem* items, int nitems,
+                      int S, hipStream_t st);
 
 }  // namespace fk
