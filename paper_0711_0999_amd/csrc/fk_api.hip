@@ -285,6 +285,7 @@ template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
 struct Aux {
   hipStream_t st2 = nullptr;
   hipEvent_t evN = nullptr, evP = nullptr;
+  bool lookahead = false;  // factor the next block on st2 (else in order on st)
 };
 
 // Invert matrices 0..nmat-1 of the batch in place (permuted storage).  The
@@ -312,19 +313,23 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
                              nmat * b.cntN[S], S, st)) != hipSuccess)
         return e;
       ++nl;
-      if ((e = hipEventRecord(ax.evN, st)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(ax.st2, ax.evN, 0)) != hipSuccess) return e;
+      hipStream_t ps = ax.lookahead ? ax.st2 : st;
+      if (ax.lookahead) {
+        if ((e = hipEventRecord(ax.evN, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ax.st2, ax.evN, 0)) != hipSuccess) return e;
+      }
       if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, S + 1, b.status,
-                            ax.st2)) != hipSuccess)
+                            ps)) != hipSuccess)
         return e;
       ++nl;
-      if ((e = hipEventRecord(ax.evP, ax.st2)) != hipSuccess) return e;
+      if (ax.lookahead && (e = hipEventRecord(ax.evP, ax.st2)) != hipSuccess) return e;
     }
     if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offB[S],
                            nmat * b.cntB[S], S, st)) != hipSuccess)
       return e;
     ++nl;
-    if (next && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess) return e;
+    if (next && ax.lookahead && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess)
+      return e;
   }
   if (ev_steps && (e = hipEventRecord(ev_steps[1], st)) != hipSuccess) return e;
   if (launches) *launches += nl;
@@ -370,6 +375,14 @@ struct fk_ctx {
   Batch<float> b32;            // lattice batch (complex64), lazily
   Batch<double> imp;           // impurity inversions (2 slots)
   Aux aux;                     // look-ahead stream and events
+  // FP64 refinement buffers of the mixed path (ir_cap matrices)
+  int ir_cap = 0;
+  c64* ir_x = nullptr;
+  c64* ir_p = nullptr;
+  c64* ir_y = nullptr;
+  c64* ir_tsub = nullptr;
+  c64* ir_tcor = nullptr;
+  int* d_iota = nullptr;
   size_t batch_bytes = 0;
   int want_batch = 0;
 
@@ -489,7 +502,7 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
                                c->d_rho + k0, nmat, n, c->d_gloc, k0 > 0 ? 1 : 0,
                                c->st));
     HIPCHK(c, launch_current<T>(b.x, b.stride, b.ld, b.piv, b.rowcol, n, c->tab,
-                                k0, nmat, c->ci.n_t, c->d_cur, c->st));
+                                k0, nmat, c->ci.n_t, n, c->d_cur, c->st));
     HIPCHK(c, hipEventRecord(c->ev[3], c->st));
     s = check_status(c, b.status, nmat, k0, "lattice inversion");
     if (s != FK_OK) return s;
@@ -507,6 +520,104 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
   if (!(mx <= std::numeric_limits<double>::max()))
     return set_err(c, FK_ENONFINITE, "G_loc has non-finite entries");
   if (ir_out) *ir_out = 0.0;
+  c->have_gloc = true;
+  return FK_OK;
+}
+
+// Mixed lattice step: complex64 build and inversion, then ir_steps FP64
+// refinement steps X <- X + X (I - A X), FP64 reduction.
+fk_status lattice_step_mixed(fk_ctx* c, double* ir_out) {
+  const int n = c->ci.n_c, ir = c->ir_steps;
+  const size_t nn = (size_t)n * n;
+  // batch size: complex64 matrix + side buffer, plus three FP64 matrices when
+  // refining
+  const size_t per = sizeof(c32) * (nn + (size_t)kNBO * n) + 2 * sizeof(int) * n +
+                     (ir > 0 ? 3 * sizeof(c64) * nn + sizeof(c64) * (n + 1) : 0);
+  size_t cap = c->batch_bytes / per;
+  if (c->want_batch > 0) cap = (size_t)c->want_batch;
+  cap = std::max<size_t>(1, std::min<size_t>(cap, c->npts));
+  const size_t nb = (c->npts + cap - 1) / cap;
+  cap = (c->npts + nb - 1) / nb;
+  Batch<float>& b = c->b32;
+  if (!b.x || b.cap != (int)cap) HIPCHK(c, batch_alloc(b, (int)cap, n));
+  if (ir > 0 && c->ir_cap != (int)cap) {
+    c64** bufs[] = {&c->ir_x, &c->ir_p, &c->ir_y};
+    for (c64** q : bufs) {
+      if (*q) (void)hipFree(*q);
+      *q = nullptr;
+      HIPCHK(c, hipMalloc(q, sizeof(c64) * nn * cap));
+    }
+    if (c->ir_tsub) (void)hipFree(c->ir_tsub);
+    if (c->ir_tcor) (void)hipFree(c->ir_tcor);
+    c->ir_tsub = c->ir_tcor = nullptr;
+    HIPCHK(c, hipMalloc(&c->ir_tsub, sizeof(c64) * (size_t)n * cap));
+    HIPCHK(c, hipMalloc(&c->ir_tcor, sizeof(c64) * cap));
+    c->ir_cap = (int)cap;
+  }
+  for (double& t : c->times) t = 0.0;
+  int launches = 0;
+  double resid = 0.0;
+  fk_status s;
+  HIPCHK(c, launch_sigma_weight(c->d_sigma, c->d_w, c->d_sigt, n, c->st));
+  HIPCHK(c, fill_f64(c->d_cur, 0.0, (size_t)c->ci.n_t, c->st));
+  for (int k0 = 0; k0 < c->npts; k0 += b.cap) {
+    const int nmat = std::min(b.cap, c->npts - k0);
+    HIPCHK(c, hipEventRecord(c->ev[0], c->st));
+    HIPCHK(c, launch_build<float>(c->d_sigt, c->tab, k0, nmat, b.x, b.stride, b.ld,
+                                  n, c->st));
+    HIPCHK(c, hipEventRecord(c->ev[1], c->st));
+    HIPCHK(c, batch_invert<float>(b, nmat, c->st, c->aux, &launches, &c->ev[6]));
+    HIPCHK(c, hipEventRecord(c->ev[2], c->st));
+    if (ir == 0) {
+      HIPCHK(c, hipEventRecord(c->ev[3], c->st));
+      HIPCHK(c, launch_reduce<float>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
+                                     c->d_rho + k0, nmat, n, c->d_gloc,
+                                     k0 > 0 ? 1 : 0, c->st));
+      HIPCHK(c, launch_current<float>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
+                                      c->tab, k0, nmat, c->ci.n_t, n, c->d_cur,
+                                      c->st));
+    } else {
+      HIPCHK(c, launch_ttab(c->tab, k0, nmat, n, c->ir_tsub, c->ir_tcor, c->st));
+      HIPCHK(c, launch_unpermute<float>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
+                                        nmat, c->ir_x, c->st));
+      c64* X = c->ir_x;
+      c64* Y = c->ir_y;
+      for (int it = 0; it < ir; ++it) {
+        HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
+        HIPCHK(c, launch_bgemm(c->ir_p, nullptr, 0.0, c->d_sigt, 0, X, n, nmat,
+                               c->st));
+        HIPCHK(c, launch_residual(c->ir_p, X, c->ir_tsub, c->ir_tcor, n, nmat,
+                                  c->d_key, c->st));
+        HIPCHK(c, launch_bgemm(Y, X, 1.0, X, nn, c->ir_p, n, nmat, c->st));
+        std::swap(X, Y);
+        const double r = read_key(c, &s);
+        if (s != FK_OK) return s;
+        if (it == ir - 1) resid = std::max(resid, r);
+      }
+      HIPCHK(c, hipEventRecord(c->ev[3], c->st));
+      HIPCHK(c, launch_reduce<double>(X, nn, n, c->d_iota, c->d_iota, 0,
+                                      c->d_rho + k0, nmat, n, c->d_gloc,
+                                      k0 > 0 ? 1 : 0, c->st));
+      HIPCHK(c, launch_current<double>(X, nn, n, c->d_iota, c->d_iota, 0, c->tab,
+                                       k0, nmat, c->ci.n_t, n, c->d_cur, c->st));
+    }
+    HIPCHK(c, hipEventRecord(c->ev[4], c->st));
+    s = check_status(c, b.status, nmat, k0, "complex64 inversion");
+    if (s != FK_OK) return s;
+    c->times[0] += elapsed(c->ev[0], c->ev[1]);
+    c->times[1] += elapsed(c->ev[1], c->ev[2]);
+    c->times[2] += elapsed(c->ev[2], c->ev[3]);
+    c->times[3] += elapsed(c->ev[3], c->ev[4]);
+    c->times[6] += elapsed(c->ev[6], c->ev[7]);
+  }
+  c->times[5] = launches;
+  HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
+  HIPCHK(c, launch_maxabs(c->d_gloc, nullptr, nn, c->d_key, c->st));
+  const double mx = read_key(c, &s);
+  if (s != FK_OK) return s;
+  if (!(mx <= std::numeric_limits<double>::max()))
+    return set_err(c, FK_ENONFINITE, "G_loc has non-finite entries");
+  if (ir_out) *ir_out = resid;
   c->have_gloc = true;
   return FK_OK;
 }
@@ -591,6 +702,10 @@ void free_ctx(fk_ctx* c) {
   for (double* p : ds)
     if (p) (void)hipFree(p);
   if (c->d_tpos) (void)hipFree(c->d_tpos);
+  c64* irs[] = {c->ir_x, c->ir_p, c->ir_y, c->ir_tsub, c->ir_tcor};
+  for (c64* p : irs)
+    if (p) (void)hipFree(p);
+  if (c->d_iota) (void)hipFree(c->d_iota);
   if (c->d_key) (void)hipFree(c->d_key);
   batch_free(c->b64);
   batch_free(c->b32);
@@ -713,6 +828,11 @@ extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
   if (e == hipSuccess) e = upload(&c->d_tpos, tp.data(), sizeof(int) * n_t);
   if (e == hipSuccess) e = upload(&c->d_coef, coef, sizeof coef);
   if (e == hipSuccess) e = hipMalloc(&c->d_key, sizeof(unsigned long long));
+  if (e == hipSuccess) {
+    std::vector<int> iota(n);
+    for (int j = 0; j < n; ++j) iota[j] = j;
+    e = upload(&c->d_iota, iota.data(), sizeof(int) * n);
+  }
   for (hipEvent_t& ev : c->ev)
     if (e == hipSuccess) e = hipEventCreate(&ev);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux.st2, hipStreamNonBlocking);
@@ -745,6 +865,7 @@ extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
     if (v > 0) bb = (size_t)v;
   }
   c->batch_bytes = bb;
+  if (const char* s = getenv("FKDMFT_LOOKAHEAD")) c->aux.lookahead = atoi(s) != 0;
   *out = c;
   return FK_OK;
 }
@@ -831,7 +952,8 @@ extern "C" fk_status fk_set_switch(fk_ctx* c, double switch_tol) {
 extern "C" fk_status fk_compute_gloc(fk_ctx* c, fk_precision prec, double* ir_out) {
   if (!c) return FK_EINVAL;
   if (prec == FK_FP64) return lattice_step<double>(c, ir_out);
-  return set_err(c, FK_EINVAL, "precision %d not available", (int)prec);
+  if (prec == FK_MIXED) return lattice_step_mixed(c, ir_out);
+  return set_err(c, FK_EINVAL, "unknown precision %d", (int)prec);
 }
 
 extern "C" fk_status fk_get_current(const fk_ctx* cc, double* t, double* j,

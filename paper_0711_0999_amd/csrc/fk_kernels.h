@@ -39,7 +39,7 @@ template <typename TI>
 hipError_t launch_current(const cplx<TI>* xbuf, size_t mat_stride, int ld,
                           const int* piv, const int* rowcol, int istride,
                           const PointTables& tab, int k0, int nmat, int n_t,
-                          double* cur, hipStream_t st);
+                          int n, double* cur, hipStream_t st);
 hipError_t launch_maxabs(const c64* a, const c64* b, size_t total,
                          unsigned long long* key, hipStream_t st);
 hipError_t launch_right_weight(const c64* src, const c64* w, c64* dst, int ld,
@@ -51,5 +51,18 @@ hipError_t launch_shifted_pair(const c64* g0inv, double d0, double d1, c64* x0,
 hipError_t launch_sigma_new(const c64* g0inv, const c64* ginv, const c64* w,
                             c64* sigma, int n, unsigned long long* key,
                             hipStream_t st);
+
+hipError_t launch_ttab(const PointTables& tab, int k0, int nmat, int n,
+                       c64* tsub, c64* tcor, hipStream_t st);
+template <typename TI>
+hipError_t launch_unpermute(const cplx<TI>* x, size_t xstride, int ld,
+                            const int* piv, const int* rowcol, int n, int nmat,
+                            c64* out, hipStream_t st);
+hipError_t launch_bgemm(c64* C, const c64* Cin, double beta, const c64* A,
+                        size_t sA, const c64* B, int n, int nmat,
+                        hipStream_t st);
+hipError_t launch_residual(c64* P, const c64* X, const c64* tsub,
+                           const c64* tcor, int n, int nmat,
+                           unsigned long long* key, hipStream_t st);
 
 }  // namespace fk

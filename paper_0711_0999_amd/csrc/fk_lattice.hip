@@ -50,6 +50,43 @@ __device__ inline c64 cexp_minus_i(c64 q, double extra_real) {
   return r;
 }
 
+// Subdiagonal entry T[i][i-1] (i >= 1) and corner T[0][n-1] of G0_k^-1.
+__device__ inline c64 t_sub(const PointTables& tab, int k, int i) {
+  const double eps = tab.eps[k], ebar = tab.ebar[k];
+  const c64 da = tab.da[i], dg = tab.dg[i], dz = tab.dz[i];
+  c64 q;
+  q.re = eps * da.re + ebar * dg.re - tab.mu * dz.re;
+  q.im = eps * da.im + ebar * dg.im - tab.mu * dz.im;
+  const c64 ex = cexp_minus_i(q, 0.0);
+  return c64{ex.im, -ex.re};  // -i * ex
+}
+__device__ inline c64 t_corner(const PointTables& tab, int k) {
+  const double eps = tab.eps[k], ebar = tab.ebar[k];
+  c64 q;
+  q.re = eps * tab.ca.re + ebar * tab.cg.re - tab.mu * tab.cz.re;
+  q.im = eps * tab.ca.im + ebar * tab.cg.im - tab.mu * tab.cz.im;
+  const c64 ex = cexp_minus_i(q, -tab.beta * (eps - tab.mu));
+  return c64{-ex.im, ex.re};  // +i * ex
+}
+
+// tsub[m][i] = T_k[i][i-1] (i >= 1), tcor[m] = T_k[0][n-1] for k = k0 + m
+__global__ void k_ttab(const PointTables tab, int k0, int nmat, int n,
+                       c64* __restrict__ tsub, c64* __restrict__ tcor) {
+  const int m = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += gridDim.x * blockDim.x) {
+    tsub[(size_t)m * n + i] = (i >= 1) ? t_sub(tab, k0 + m, i) : c64{0.0, 0.0};
+    if (i == 0) tcor[m] = t_corner(tab, k0 + m);
+  }
+}
+
+hipError_t launch_ttab(const PointTables& tab, int k0, int nmat, int n,
+                       c64* tsub, c64* tcor, hipStream_t st) {
+  hipLaunchKernelGGL(k_ttab, dim3((n + 255) / 256, nmat), dim3(256), 0, st, tab,
+                     k0, nmat, n, tsub, tcor);
+  return hipGetLastError();
+}
+
 template <typename TO>
 __global__ void k_build(const c64* __restrict__ sigt,
                         const PointTables tab, int k0, int nmat,
@@ -69,25 +106,9 @@ __global__ void k_build(const c64* __restrict__ sigt,
     if (j == i) {
       a.im += 1.0;
     } else if (j == i - 1 || (i == 0 && j == n - 1)) {
-      const int k = k0 + m;
-      const double eps = tab.eps[k], ebar = tab.ebar[k];
-      c64 q;
-      double extra = 0.0;
-      if (j == i - 1) {
-        const c64 da = tab.da[i], dg = tab.dg[i], dz = tab.dz[i];
-        q.re = eps * da.re + ebar * dg.re - tab.mu * dz.re;
-        q.im = eps * da.im + ebar * dg.im - tab.mu * dz.im;
-        const c64 ex = cexp_minus_i(q, 0.0);
-        a.re += ex.im;   // -i * ex
-        a.im += -ex.re;
-      } else {
-        q.re = eps * tab.ca.re + ebar * tab.cg.re - tab.mu * tab.cz.re;
-        q.im = eps * tab.ca.im + ebar * tab.cg.im - tab.mu * tab.cz.im;
-        extra = -tab.beta * (eps - tab.mu);
-        const c64 ex = cexp_minus_i(q, extra);
-        a.re += -ex.im;  // +i * ex
-        a.im += ex.re;
-      }
+      const c64 t = (j == i - 1) ? t_sub(tab, k0 + m, i) : t_corner(tab, k0 + m);
+      a.re += t.re;
+      a.im += t.im;
     }
     cplx<TO> o;
     o.re = (TO)a.re;
@@ -134,7 +155,7 @@ __global__ void k_current(const cplx<TI>* __restrict__ xbuf, size_t mat_stride,
                           int ld, const int* __restrict__ pivbuf,
                           const int* __restrict__ rowcolbuf, int istride,
                           const PointTables tab, int k0, int nmat, int n_t,
-                          double* __restrict__ cur) {
+                          int n, double* __restrict__ cur) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_t) return;
   const int pcol = 2 * n_t - i;
@@ -145,7 +166,7 @@ __global__ void k_current(const cplx<TI>* __restrict__ xbuf, size_t mat_stride,
     const int k = k0 + m;
     const int r = pivbuf[(size_t)m * istride + i];
     const int c = rowcolbuf[(size_t)m * istride + pcol];
-    if (r < 0 || c < 0 || r >= istride || c >= istride) {
+    if (r < 0 || c < 0 || r >= n || c >= n) {
       acc = __builtin_nan("");
       continue;
     }
@@ -312,10 +333,10 @@ template <typename TI>
 hipError_t launch_current(const cplx<TI>* xbuf, size_t mat_stride, int ld,
                           const int* piv, const int* rowcol, int istride,
                           const PointTables& tab, int k0, int nmat, int n_t,
-                          double* cur, hipStream_t st) {
+                          int n, double* cur, hipStream_t st) {
   hipLaunchKernelGGL(k_current<TI>, dim3((n_t + 127) / 128), dim3(128), 0, st,
                      xbuf, mat_stride, ld, piv, rowcol, istride, tab, k0, nmat,
-                     n_t, cur);
+                     n_t, n, cur);
   return hipGetLastError();
 }
 
@@ -370,9 +391,11 @@ template hipError_t launch_reduce<float>(const c32*, size_t, int, const int*,
                                          int, c64*, int, hipStream_t);
 template hipError_t launch_current<double>(const c64*, size_t, int, const int*,
                                            const int*, int, const PointTables&,
-                                           int, int, int, double*, hipStream_t);
+                                           int, int, int, int, double*,
+                                           hipStream_t);
 template hipError_t launch_current<float>(const c32*, size_t, int, const int*,
                                           const int*, int, const PointTables&,
-                                          int, int, int, double*, hipStream_t);
+                                          int, int, int, int, double*,
+                                          hipStream_t);
 
 }  // namespace fk
