@@ -171,6 +171,40 @@ fk_status fk_set_switch(fk_ctx* ctx, double switch_tol);
  * inversion kernel launches, out[6] summed duration of the step kernels. */
 fk_status fk_timings(const fk_ctx* ctx, double* out7);
 
+/* ---- many instances in one sweep ----------------------------------------- */
+
+/* A set of independent DMFT problems (contours and models may differ: uneven
+ * N_c, Gauss-Hermite orders, U, E) iterated together.  In every sweep the
+ * lattice steps of all active instances share uneven batched inversions (one
+ * launch per Gauss-Jordan step over all (instance, point, tile) work items),
+ * the impurity updates share batched inversions as well, and each instance
+ * retires after the iteration whose delta falls below tol.  Same semantics per
+ * instance as fk_iterate with FK_FP64.  The batch owns its stream and device
+ * memory; instance i's state is reachable as an fk_ctx through
+ * fk_batch_instance (owned by the batch: do not destroy it), so fk_get_gloc,
+ * fk_get_sigma, fk_set_sigma and fk_get_current apply to it. */
+typedef struct fk_batch fk_batch;
+fk_status fk_batch_create(int n_inst, const fk_contour* contours,
+                          const fk_model* models, fk_batch** out);
+fk_status fk_batch_destroy(fk_batch* b);                 /* NULL-safe */
+const char* fk_batch_last_error(const fk_batch* b);
+fk_status fk_batch_instance(const fk_batch* b, int i, fk_ctx** ctx);
+/* Device memory for the lattice inversions of one chunk of a sweep (bytes,
+ * default FKDMFT_BATCH_BYTES or 24 GiB): larger chunks, fewer launches. */
+fk_status fk_batch_set_chunk_bytes(fk_batch* b, double bytes);
+/* Mark every instance active again with its iteration count at zero (Sigma kept). */
+fk_status fk_batch_reset(fk_batch* b);
+/* Run up to max_sweeps sweeps or until every instance has converged.
+ * use_graph = 1 records the sweep into a hipGraph (re-recorded when the set of
+ * active instances changes) and replays it; 0 launches eagerly.
+ * iters[n_inst] and deltas[n_inst] (nullable) receive each instance's
+ * iteration count and last delta (+inf after its first iteration). */
+fk_status fk_batch_iterate(fk_batch* b, int max_sweeps, double tol,
+                           int use_graph, int* sweeps_out, int* iters,
+                           double* deltas);
+/* out4: last sweep ms, total sweep ms, graph recordings, last recording ms. */
+fk_status fk_batch_timings(const fk_batch* b, double* out4);
+
 #ifdef __cplusplus
 }
 #endif

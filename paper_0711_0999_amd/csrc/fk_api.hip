@@ -4,6 +4,7 @@
 #include "../../include/fkdmft.h"
 #include "fk_internal.h"
 #include "fk_kernels.h"
+#include "fk_ctx.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -37,10 +38,6 @@ int sturm_count(int n, double x) {
   return cnt;
 }
 
-struct ContourInfo {
-  int n_t = 0, n_tau = 0, n_c = 0;
-  std::vector<double> zr, zi, wr, wi;
-};
 
 bool integral_ratio(double span, double step, int* out) {
   if (!(step > 0.0) || !(span > 0.0)) return false;
@@ -156,243 +153,7 @@ extern "C" const char* fk_status_string(fk_status s) {
   }
 }
 
-// ==================================================================== device ==
-namespace {
 
-__global__ void k_fill_int(int* p, int v, size_t n) {
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
-       e += (size_t)gridDim.x * blockDim.x)
-    p[e] = v;
-}
-__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) p[e] = v;
-}
-__global__ void k_fill_f64(double* p, double v, size_t n) {
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
-       e += (size_t)gridDim.x * blockDim.x)
-    p[e] = v;
-}
-
-hipError_t fill_int(int* p, int v, size_t n, hipStream_t st) {
-  size_t g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_fill_int, dim3((int)g), dim3(256), 0, st, p, v, n);
-  return hipGetLastError();
-}
-hipError_t fill_u64(unsigned long long* p, unsigned long long v, int n,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_u64, dim3((n + 63) / 64), dim3(64), 0, st, p, v, n);
-  return hipGetLastError();
-}
-hipError_t fill_f64(double* p, double v, size_t n, hipStream_t st) {
-  size_t g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_fill_f64, dim3((int)g), dim3(256), 0, st, p, v, n);
-  return hipGetLastError();
-}
-
-// A batch of same-size matrices for the blocked Gauss-Jordan inversion.
-template <typename T> struct Batch {
-  int cap = 0, n = 0, ld = 0;
-  size_t stride = 0;
-  cplx<T>* x = nullptr;
-  cplx<T>* bbuf = nullptr;     // gathered pivot rows, kNBO x ld per matrix
-  int* piv = nullptr;
-  int* rowcol = nullptr;
-  int* status = nullptr;
-  MatDesc* descs = nullptr;
-  TileItem* items = nullptr;
-  // per outer step S: tile items of the next block's columns ("narrow") and of
-  // all other columns ("big"), matrix-major so a prefix serves fewer matrices
-  std::vector<int> offN, cntN, offB, cntB;
-  int nouter = 0;
-};
-
-template <typename T> void batch_free(Batch<T>& b) {
-  if (b.x) (void)hipFree(b.x);
-  if (b.bbuf) (void)hipFree(b.bbuf);
-  if (b.piv) (void)hipFree(b.piv);
-  if (b.rowcol) (void)hipFree(b.rowcol);
-  if (b.status) (void)hipFree(b.status);
-  if (b.descs) (void)hipFree(b.descs);
-  if (b.items) (void)hipFree(b.items);
-  b = Batch<T>();
-}
-
-template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
-  batch_free(b);
-  b.cap = cap;
-  b.n = n;
-  b.ld = n;
-  b.stride = (size_t)n * n;
-  b.nouter = (n + kNBO - 1) / kNBO;
-  hipError_t e;
-  if ((e = hipMalloc(&b.x, sizeof(cplx<T>) * b.stride * cap)) != hipSuccess) return e;
-  if ((e = hipMalloc(&b.bbuf, sizeof(cplx<T>) * (size_t)kNBO * b.ld * cap)) != hipSuccess)
-    return e;
-  if ((e = hipMalloc(&b.piv, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
-  if ((e = hipMalloc(&b.rowcol, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
-  if ((e = hipMalloc(&b.status, sizeof(int) * cap)) != hipSuccess) return e;
-  std::vector<MatDesc> d(cap);
-  for (int m = 0; m < cap; ++m) {
-    d[m].xoff = (long long)b.stride * m;
-    d[m].boff = (long long)kNBO * b.ld * m;
-    d[m].n = n;
-    d[m].ld = b.ld;
-    d[m].ioff = n * m;
-    d[m].status_idx = m;
-  }
-  if ((e = hipMalloc(&b.descs, sizeof(MatDesc) * cap)) != hipSuccess) return e;
-  if ((e = hipMemcpy(b.descs, d.data(), sizeof(MatDesc) * cap,
-                     hipMemcpyHostToDevice)) != hipSuccess)
-    return e;
-  const int nt = (n + kTile - 1) / kTile;
-  std::vector<TileItem> it;
-  b.offN.assign(b.nouter, 0);
-  b.cntN.assign(b.nouter, 0);
-  b.offB.assign(b.nouter, 0);
-  b.cntB.assign(b.nouter, 0);
-  for (int S = 0; S < b.nouter; ++S) {
-    for (int pass = 0; pass < 2; ++pass) {
-      (pass ? b.offB : b.offN)[S] = (int)it.size();
-      int per = 0;
-      for (int m = 0; m < cap; ++m) {
-        per = 0;
-        for (int tc = 0; tc < nt; ++tc) {
-          const int blk = tc / (kNBO / kTile);
-          const bool narrow = blk == S + 1;
-          const bool big = blk != S && blk != S + 1;
-          if (pass == 0 ? !narrow : !big) continue;
-          for (int tr = 0; tr < nt; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
-          per += nt;
-        }
-      }
-      (pass ? b.cntB : b.cntN)[S] = per;
-    }
-  }
-  if ((e = hipMalloc(&b.items, sizeof(TileItem) * std::max<size_t>(it.size(), 1))) !=
-      hipSuccess)
-    return e;
-  if (it.empty()) return hipSuccess;
-  return hipMemcpy(b.items, it.data(), sizeof(TileItem) * it.size(),
-                   hipMemcpyHostToDevice);
-}
-
-// Side stream and events of the look-ahead (default priority).
-struct Aux {
-  hipStream_t st2 = nullptr;
-  hipEvent_t evN = nullptr, evP = nullptr;
-  bool lookahead = false;  // factor the next block on st2 (else in order on st)
-};
-
-// Invert matrices 0..nmat-1 of the batch in place (permuted storage).  The
-// next outer block is factored on the side stream while the big update of
-// the current block runs on st.  ev_steps (nullable) brackets the kernels.
-template <typename T>
-hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
-                        int* launches, hipEvent_t* ev_steps = nullptr) {
-  hipError_t e;
-  if ((e = fill_int(b.rowcol, -1, (size_t)b.n * nmat, st)) != hipSuccess) return e;
-  if ((e = fill_int(b.status, 0, (size_t)nmat, st)) != hipSuccess) return e;
-  if (ev_steps && (e = hipEventRecord(ev_steps[0], st)) != hipSuccess) return e;
-  int nl = 0;
-  if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, 0, b.status, st)) !=
-      hipSuccess)
-    return e;
-  ++nl;
-  for (int S = 0; S < b.nouter; ++S) {
-    const bool next = S + 1 < b.nouter;
-    if ((e = gje_gather<T>(b.x, b.bbuf, b.piv, b.descs, nmat, S, st)) != hipSuccess)
-      return e;
-    ++nl;
-    if (next) {
-      if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offN[S],
-                             nmat * b.cntN[S], S, st)) != hipSuccess)
-        return e;
-      ++nl;
-      hipStream_t ps = ax.lookahead ? ax.st2 : st;
-      if (ax.lookahead) {
-        if ((e = hipEventRecord(ax.evN, st)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(ax.st2, ax.evN, 0)) != hipSuccess) return e;
-      }
-      if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, S + 1, b.status,
-                            ps)) != hipSuccess)
-        return e;
-      ++nl;
-      if (ax.lookahead && (e = hipEventRecord(ax.evP, ax.st2)) != hipSuccess) return e;
-    }
-    if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offB[S],
-                           nmat * b.cntB[S], S, st)) != hipSuccess)
-      return e;
-    ++nl;
-    if (next && ax.lookahead && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess)
-      return e;
-  }
-  if (ev_steps && (e = hipEventRecord(ev_steps[1], st)) != hipSuccess) return e;
-  if (launches) *launches += nl;
-  return hipSuccess;
-}
-
-}  // namespace
-
-// ======================================================================= ctx ==
-struct fk_ctx {
-  fk_contour c;
-  fk_model m;
-  ContourInfo ci;
-  int npts = 0;
-  std::vector<double> eps, ebar, rho;
-  hipStream_t st = nullptr;
-  bool own_stream = false;
-  std::string err;
-
-  // device
-  c64* d_w = nullptr;          // weights W (N_c)
-  c64* d_sigma = nullptr;      // Sigma values
-  c64* d_sigt = nullptr;       // W Sigma W
-  c64* d_gloc = nullptr;
-  c64* d_gprev = nullptr;
-  c64* d_g0inv = nullptr;      // impurity scratch
-  c64* d_tmp = nullptr;        // impurity scratch
-  double* d_cur = nullptr;     // j(t), N_t
-  double* d_eps = nullptr;
-  double* d_ebar = nullptr;
-  double* d_rho = nullptr;
-  c64* d_da = nullptr;
-  c64* d_dg = nullptr;
-  c64* d_dz = nullptr;
-  double* d_cos = nullptr;
-  double* d_sin = nullptr;
-  int* d_tpos = nullptr;
-  double* d_coef = nullptr;    // {1, 1 - w1, w1}
-  unsigned long long* d_key = nullptr;
-  PointTables tab;
-
-  Batch<double> b64;           // lattice batch (complex128)
-  Batch<float> b32;            // lattice batch (complex64), lazily
-  Batch<double> imp;           // impurity inversions (2 slots)
-  Aux aux;                     // look-ahead stream and events
-  // FP64 refinement buffers of the mixed path (ir_cap matrices)
-  int ir_cap = 0;
-  c64* ir_x = nullptr;
-  c64* ir_p = nullptr;
-  c64* ir_y = nullptr;
-  c64* ir_tsub = nullptr;
-  c64* ir_tcor = nullptr;
-  int* d_iota = nullptr;
-  size_t batch_bytes = 0;
-  int want_batch = 0;
-
-  bool have_gloc = false;
-  bool have_prev = false;
-  int ir_steps = 1;
-  double switch_tol = 1e-5;
-  double times[7] = {0, 0, 0, 0, 0, 0, 0};
-  hipEvent_t ev[8];
-};
 
 namespace {
 

@@ -1,0 +1,613 @@
+// Multi-instance sweep: several DMFT problems (different contours, U, E) run
+// their self-consistency loops together.  Every lattice step of a sweep puts
+// the point matrices of all active instances into uneven batches, so each
+// Gauss-Jordan step is one launch over (instance, point, tile) work items;
+// the impurity updates of all instances share batched inversions too.  The
+// sweep is recorded once into a hipGraph and replayed; it is re-recorded when
+// an instance converges and retires.
+#include "fk_ctx.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstring>
+#include <chrono>
+#include <limits>
+#include <string>
+#include <vector>
+
+using namespace fk;
+
+namespace fk {
+
+// Per-instance device view for the batched impurity update.
+struct InstDev {
+  c64* gloc;
+  c64* gprev;
+  c64* sigma;
+  const c64* w;
+  c64* g0inv;
+  c64* tmp;
+  int n;
+  double d0, d1, w1;
+  long long s0, s1;  // element offsets of the two impurity slots
+  int i0, i1;        // int offsets of their pivot arrays
+  int key;           // slot of this instance in the key array (2 per instance)
+};
+
+__device__ inline c64 cmulw(c64 a, c64 b) {
+  return c64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// Stages of the Falicov-Kimball update in right-weighted form (A -> A W):
+//   0: slot0 = G_loc W
+//   1: g0inv = inv(slot0) + Sigma W
+//   2: slot0 = g0inv + d0 S, slot1 = g0inv + d1 S  (S the point-split delta)
+//   3: tmp = (1 - w1) inv(slot0) + w1 inv(slot1)
+//   4: slot0 = tmp
+//   5: Sigma <- (g0inv - inv(slot0)) W^-1, key = max |Sigma change|
+__global__ void k_imp_stage(const InstDev* __restrict__ inst, int stage,
+                            c64* __restrict__ ximp, const int* __restrict__ piv,
+                            const int* __restrict__ rc,
+                            unsigned long long* __restrict__ keys) {
+  const InstDev d = inst[blockIdx.y];
+  const int n = d.n;
+  const size_t total = (size_t)n * n;
+  double mx = 0.0;
+  bool bad = false;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e - (e / n) * n);
+    const c64 wj = d.w[j];
+    if (stage == 0) {
+      ximp[d.s0 + e] = cmulw(d.gloc[e], wj);
+    } else if (stage == 1) {
+      const c64 x0 = ximp[d.s0 + (size_t)piv[d.i0 + i] * n + rc[d.i0 + j]];
+      const c64 sw = cmulw(d.sigma[e], wj);
+      d.g0inv[e] = c64{x0.re + sw.re, x0.im + sw.im};
+    } else if (stage == 2) {
+      double s = 0.0;
+      if (j == i - 1) s = 1.0;
+      if (i == 0 && j == n - 1) s = -1.0;
+      const c64 g = d.g0inv[e];
+      ximp[d.s0 + e] = c64{g.re + d.d0 * s, g.im};
+      ximp[d.s1 + e] = c64{g.re + d.d1 * s, g.im};
+    } else if (stage == 3) {
+      const c64 a = ximp[d.s0 + (size_t)piv[d.i0 + i] * n + rc[d.i0 + j]];
+      const c64 b = ximp[d.s1 + (size_t)piv[d.i1 + i] * n + rc[d.i1 + j]];
+      d.tmp[e] = c64{(1.0 - d.w1) * a.re + d.w1 * b.re, (1.0 - d.w1) * a.im + d.w1 * b.im};
+    } else if (stage == 4) {
+      ximp[d.s0 + e] = d.tmp[e];
+    } else {
+      const c64 gi = ximp[d.s0 + (size_t)piv[d.i0 + i] * n + rc[d.i0 + j]];
+      const c64 g = d.g0inv[e];
+      const c64 df{g.re - gi.re, g.im - gi.im};
+      const double den = wj.re * wj.re + wj.im * wj.im;
+      const c64 s{(df.re * wj.re + df.im * wj.im) / den,
+                  (df.im * wj.re - df.re * wj.im) / den};
+      const c64 old = d.sigma[e];
+      const double dr = s.re - old.re, di = s.im - old.im;
+      const double a = sqrt(dr * dr + di * di);
+      if (!(a <= 1.79769313486231570815e308)) bad = true;
+      else if (a > mx) mx = a;
+      d.sigma[e] = s;
+    }
+  }
+  if (stage == 5) {
+    unsigned long long k = bad ? 0x7ff8000000000000ULL
+                               : (unsigned long long)__double_as_longlong(mx);
+    for (int off = 32; off >= 1; off >>= 1) {
+      const unsigned long long o = __shfl_xor(k, off);
+      k = o > k ? o : k;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(&keys[d.key + 1], k);
+  }
+}
+
+// delta = max |G_loc - G_prev| into keys[key], then G_prev <- G_loc
+__global__ void k_delta(const InstDev* __restrict__ inst,
+                        unsigned long long* __restrict__ keys) {
+  const InstDev d = inst[blockIdx.y];
+  const size_t total = (size_t)d.n * d.n;
+  double mx = 0.0;
+  bool bad = false;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const c64 g = d.gloc[e], p = d.gprev[e];
+    const double dr = g.re - p.re, di = g.im - p.im;
+    const double a = sqrt(dr * dr + di * di);
+    if (!(a <= 1.79769313486231570815e308)) bad = true;
+    else if (a > mx) mx = a;
+    d.gprev[e] = g;
+  }
+  unsigned long long k = bad ? 0x7ff8000000000000ULL
+                             : (unsigned long long)__double_as_longlong(mx);
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(k, off);
+    k = o > k ? o : k;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(&keys[d.key], k);
+}
+
+}  // namespace fk
+
+// ======================================================================= batch
+struct Segment {
+  int inst, k0, cnt;
+  size_t xoff, ioff;
+};
+struct Chunk {
+  fk::Batch<double> b;   // descriptors and tile lists; storage borrowed
+  std::vector<Segment> segs;
+};
+
+struct fk_batch {
+  hipStream_t st = nullptr;
+  std::vector<fk_ctx*> inst;
+  std::vector<int> active;
+  std::vector<int> iters;
+  std::vector<double> delta;
+  std::vector<Chunk> chunks;
+  fk::Batch<double> impA, impB;   // slot0 of every active instance / both slots
+  // shared storage of the lattice chunks and of the impurity slots
+  c64* x = nullptr;
+  c64* bbuf = nullptr;
+  int* piv = nullptr;
+  int* rowcol = nullptr;
+  size_t x_cap = 0, b_cap = 0, i_cap = 0, i2_cap = 0;
+  c64* xi = nullptr;
+  c64* bi = nullptr;
+  int* pivi = nullptr;
+  int* rci = nullptr;
+  size_t xi_cap = 0, bi_cap = 0, ii_cap = 0, ii2_cap = 0;
+  int* d_status = nullptr;
+  size_t status_cap = 0;
+  int n_status = 0;
+  unsigned long long* d_keys = nullptr;
+  InstDev* d_inst = nullptr;
+  size_t inst_cap = 0;
+  int n_active_dev = 0;
+  double chunk_bytes = 24.0 * (1 << 30);
+  fk::Aux aux;
+  bool dirty = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_for_plan = false;
+  int captures = 0;
+  double capture_ms = 0.0, last_sweep_ms = 0.0, total_ms = 0.0;
+  int max_nc = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+fk_status berr(fk_batch* b, fk_status s, const char* fmt, ...) {
+  if (b) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b->err = buf;
+  }
+  return s;
+}
+
+#define BCHK(bt, expr)                                                      \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return berr((bt), e_ == hipErrorOutOfMemory ? FK_ENOMEM : FK_EDEVICE, \
+                  "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,  \
+                  __LINE__);                                                \
+  } while (0)
+
+void drop_graph(fk_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->graph_for_plan = false;
+}
+
+// Point the borrowed storage of a chunk batch at the shared buffers.
+void borrow(fk::Batch<double>& cb, c64* x, size_t xc, c64* bb, size_t bc,
+            int* pv, int* rc, size_t ic) {
+  cb.owns = false;
+  cb.x = x;
+  cb.x_cap = xc;
+  cb.bbuf = bb;
+  cb.b_cap = bc;
+  cb.piv = pv;
+  cb.rowcol = rc;
+  cb.i_cap = ic;
+}
+
+// Chunk plan for the active instances: point matrices ordered by instance,
+// cut into chunks that fit chunk_bytes; impurity slots after them.
+fk_status build_plan(fk_batch* b) {
+  drop_graph(b);
+  for (Chunk& c : b->chunks) batch_free(c.b);
+  b->chunks.clear();
+  struct Job { int inst, k; };
+  std::vector<std::vector<Job>> groups(1);
+  double used = 0.0;
+  for (int id : b->active) {
+    const fk_ctx* c = b->inst[id];
+    const double n = c->ci.n_c;
+    const double per = 16.0 * (n * n + kNBO * n) + 8.0 * n;
+    for (int k = 0; k < c->npts; ++k) {
+      if (used + per > b->chunk_bytes && !groups.back().empty()) {
+        groups.emplace_back();
+        used = 0.0;
+      }
+      groups.back().push_back(Job{id, k});
+      used += per;
+    }
+  }
+  if (groups.back().empty()) groups.pop_back();
+  // storage needs
+  size_t xmax = 0, bmax = 0, imax = 0;
+  int status = 0;
+  std::vector<std::vector<int>> sizes(groups.size()), sidx(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    size_t xs = 0, bs = 0, is = 0;
+    for (const Job& j : groups[g]) {
+      const int n = b->inst[j.inst]->ci.n_c;
+      sizes[g].push_back(n);
+      sidx[g].push_back(status++);
+      xs += (size_t)n * n;
+      bs += (size_t)kNBO * n;
+      is += n;
+    }
+    xmax = std::max(xmax, xs);
+    bmax = std::max(bmax, bs);
+    imax = std::max(imax, is);
+  }
+  BCHK(b, grow(&b->x, &b->x_cap, xmax));
+  BCHK(b, grow(&b->bbuf, &b->b_cap, bmax));
+  BCHK(b, grow(&b->piv, &b->i_cap, imax));
+  BCHK(b, grow(&b->rowcol, &b->i2_cap, imax));
+  b->chunks.resize(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    Chunk& ch = b->chunks[g];
+    borrow(ch.b, b->x, b->x_cap, b->bbuf, b->b_cap, b->piv, b->rowcol, b->i_cap);
+    BCHK(b, batch_setup_uneven(ch.b, sizes[g], sidx[g]));
+    size_t xo = 0, io = 0;
+    for (const Job& j : groups[g]) {
+      const int n = b->inst[j.inst]->ci.n_c;
+      if (ch.segs.empty() || ch.segs.back().inst != j.inst)
+        ch.segs.push_back(Segment{j.inst, j.k, 0, xo, io});
+      ch.segs.back().cnt++;
+      xo += (size_t)n * n;
+      io += n;
+    }
+  }
+  // impurity slots: slot0 of every active instance, then every slot1
+  const int na = (int)b->active.size();
+  std::vector<int> isz(2 * na), isx(2 * na);
+  size_t xs = 0, bs = 0, is = 0;
+  for (int h = 0; h < 2; ++h)
+    for (int a = 0; a < na; ++a) {
+      const int n = b->inst[b->active[a]]->ci.n_c;
+      isz[h * na + a] = n;
+      isx[h * na + a] = status++;
+      xs += (size_t)n * n;
+      bs += (size_t)kNBO * n;
+      is += n;
+    }
+  BCHK(b, grow(&b->xi, &b->xi_cap, xs));
+  BCHK(b, grow(&b->bi, &b->bi_cap, bs));
+  BCHK(b, grow(&b->pivi, &b->ii_cap, is));
+  BCHK(b, grow(&b->rci, &b->ii2_cap, is));
+  batch_free(b->impA);
+  batch_free(b->impB);
+  borrow(b->impA, b->xi, b->xi_cap, b->bi, b->bi_cap, b->pivi, b->rci, b->ii_cap);
+  borrow(b->impB, b->xi, b->xi_cap, b->bi, b->bi_cap, b->pivi, b->rci, b->ii_cap);
+  BCHK(b, batch_setup_uneven(b->impB, isz, isx));
+  std::vector<int> hsz(isz.begin(), isz.begin() + na), hsx(isx.begin(), isx.begin() + na);
+  BCHK(b, batch_setup_uneven(b->impA, hsz, hsx));
+  b->n_status = status;
+  BCHK(b, grow(&b->d_status, &b->status_cap, (size_t)status));
+  // instance views
+  std::vector<InstDev> iv(na);
+  size_t so = 0, ioff = 0;
+  std::vector<size_t> s0(na), i0(na);
+  for (int a = 0; a < na; ++a) {
+    const int n = b->inst[b->active[a]]->ci.n_c;
+    s0[a] = so;
+    i0[a] = ioff;
+    so += (size_t)n * n;
+    ioff += n;
+  }
+  for (int a = 0; a < na; ++a) {
+    fk_ctx* c = b->inst[b->active[a]];
+    const int n = c->ci.n_c;
+    InstDev& d = iv[a];
+    d.gloc = c->d_gloc;
+    d.gprev = c->d_gprev;
+    d.sigma = c->d_sigma;
+    d.w = c->d_w;
+    d.g0inv = c->d_g0inv;
+    d.tmp = c->d_tmp;
+    d.n = n;
+    d.d0 = c->m.convention == 0 ? 0.5 * c->m.U : 0.0;
+    d.d1 = c->m.convention == 0 ? -0.5 * c->m.U : -c->m.U;
+    d.w1 = c->m.w1;
+    d.s0 = (long long)s0[a];
+    d.s1 = (long long)(so + s0[a]);
+    d.i0 = (int)i0[a];
+    d.i1 = (int)(ioff + i0[a]);
+    d.key = 2 * b->active[a];
+  }
+  BCHK(b, grow(&b->d_inst, &b->inst_cap, (size_t)std::max(na, 1)));
+  if (na) BCHK(b, hipMemcpy(b->d_inst, iv.data(), sizeof(InstDev) * na, hipMemcpyHostToDevice));
+  b->n_active_dev = na;
+  b->dirty = false;
+  return FK_OK;
+}
+
+hipError_t launch_imp(fk_batch* b, int stage) {
+  int nmax = 0;
+  for (int id : b->active) nmax = std::max(nmax, b->inst[id]->ci.n_c);
+  int gx = (int)std::min<size_t>(((size_t)nmax * nmax + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_imp_stage, dim3(gx, b->n_active_dev), dim3(256), 0, b->st,
+                     b->d_inst, stage, b->xi, b->pivi, b->rci, b->d_keys);
+  return hipGetLastError();
+}
+
+// Enqueue one sweep (lattice steps of all active instances, convergence norm,
+// impurity updates) on b->st.  Stream work only: capturable into a graph.
+hipError_t record_sweep(fk_batch* b) {
+  hipError_t e;
+  if ((e = fill_int(b->d_status, 0, (size_t)b->n_status, b->st)) != hipSuccess) return e;
+  for (int id : b->active) {
+    fk_ctx* c = b->inst[id];
+    const int n = c->ci.n_c;
+    if ((e = launch_sigma_weight(c->d_sigma, c->d_w, c->d_sigt, n, b->st)) != hipSuccess)
+      return e;
+    if ((e = fill_f64(reinterpret_cast<double*>(c->d_gloc), 0.0, 2 * (size_t)n * n, b->st)) !=
+        hipSuccess)
+      return e;
+    if ((e = fill_f64(c->d_cur, 0.0, (size_t)c->ci.n_t, b->st)) != hipSuccess) return e;
+  }
+  for (Chunk& ch : b->chunks) {
+    for (const Segment& sg : ch.segs) {
+      fk_ctx* c = b->inst[sg.inst];
+      const int n = c->ci.n_c;
+      if ((e = launch_build<double>(c->d_sigt, c->tab, sg.k0, sg.cnt, b->x + sg.xoff,
+                                    (size_t)n * n, n, n, b->st)) != hipSuccess)
+        return e;
+    }
+    if ((e = batch_invert<double>(ch.b, ch.b.cap, b->st, b->aux, nullptr, nullptr,
+                                  b->d_status)) != hipSuccess)
+      return e;
+    for (const Segment& sg : ch.segs) {
+      fk_ctx* c = b->inst[sg.inst];
+      const int n = c->ci.n_c;
+      if ((e = launch_reduce<double>(b->x + sg.xoff, (size_t)n * n, n, b->piv + sg.ioff,
+                                     b->rowcol + sg.ioff, n, c->d_rho + sg.k0, sg.cnt,
+                                     n, c->d_gloc, 1, b->st)) != hipSuccess)
+        return e;
+      if ((e = launch_current<double>(b->x + sg.xoff, (size_t)n * n, n,
+                                      b->piv + sg.ioff, b->rowcol + sg.ioff, n, c->tab,
+                                      sg.k0, sg.cnt, c->ci.n_t, n, c->d_cur, b->st)) !=
+          hipSuccess)
+        return e;
+    }
+  }
+  if ((e = fill_u64(b->d_keys, 0ULL, 2 * (int)b->inst.size(), b->st)) != hipSuccess)
+    return e;
+  if (b->n_active_dev == 0) return hipSuccess;
+  int nmax = 0;
+  for (int id : b->active) nmax = std::max(nmax, b->inst[id]->ci.n_c);
+  const int gx = (int)std::min<size_t>(((size_t)nmax * nmax + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_delta, dim3(gx, b->n_active_dev), dim3(256), 0, b->st,
+                     b->d_inst, b->d_keys);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int na = b->n_active_dev;
+  if ((e = launch_imp(b, 0)) != hipSuccess) return e;
+  if ((e = batch_invert<double>(b->impA, na, b->st, b->aux, nullptr, nullptr,
+                                b->d_status)) != hipSuccess)
+    return e;
+  if ((e = launch_imp(b, 1)) != hipSuccess) return e;
+  if ((e = launch_imp(b, 2)) != hipSuccess) return e;
+  if ((e = batch_invert<double>(b->impB, 2 * na, b->st, b->aux, nullptr, nullptr,
+                                b->d_status)) != hipSuccess)
+    return e;
+  if ((e = launch_imp(b, 3)) != hipSuccess) return e;
+  if ((e = launch_imp(b, 4)) != hipSuccess) return e;
+  if ((e = batch_invert<double>(b->impA, na, b->st, b->aux, nullptr, nullptr,
+                                b->d_status)) != hipSuccess)
+    return e;
+  return launch_imp(b, 5);
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" fk_status fk_batch_create(int n_inst, const fk_contour* contours,
+                                     const fk_model* models, fk_batch** out) {
+  if (n_inst < 1 || !contours || !models || !out) return FK_EINVAL;
+  *out = nullptr;
+  fk_batch* b = new (std::nothrow) fk_batch();
+  if (!b) return FK_ENOMEM;
+  hipError_t e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return FK_EDEVICE;
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    fk_ctx* c = nullptr;
+    const fk_status s = fk_create(&contours[i], &models[i], b->st, &c);
+    if (s != FK_OK) {
+      fk_batch_destroy(b);
+      return s;
+    }
+    b->inst.push_back(c);
+    b->active.push_back(i);
+    b->max_nc = std::max(b->max_nc, c->ci.n_c);
+  }
+  b->iters.assign(n_inst, 0);
+  b->delta.assign(n_inst, std::numeric_limits<double>::infinity());
+  if (const char* s = getenv("FKDMFT_BATCH_BYTES")) {
+    const double v = atof(s);
+    if (v > 0) b->chunk_bytes = v;
+  }
+  e = hipMalloc(&b->d_keys, sizeof(unsigned long long) * 2 * n_inst);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->aux.st2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->aux.evN, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->aux.evP, hipEventDisableTiming);
+  // set the kernels' LDS attribute outside any capture
+  if (e == hipSuccess) e = gje_panel<double>(nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, b->st);
+  if (e != hipSuccess) {
+    fk_batch_destroy(b);
+    return FK_EDEVICE;
+  }
+  *out = b;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_batch_destroy(fk_batch* b) {
+  if (!b) return FK_OK;
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  drop_graph(b);
+  for (Chunk& c : b->chunks) batch_free(c.b);
+  batch_free(b->impA);
+  batch_free(b->impB);
+  void* ps[] = {b->x, b->bbuf, b->piv, b->rowcol, b->xi, b->bi, b->pivi, b->rci,
+                b->d_status, b->d_keys, b->d_inst};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  for (fk_ctx* c : b->inst) fk_destroy(c);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  if (b->aux.evN) (void)hipEventDestroy(b->aux.evN);
+  if (b->aux.evP) (void)hipEventDestroy(b->aux.evP);
+  if (b->aux.st2) (void)hipStreamDestroy(b->aux.st2);
+  if (b->st) (void)hipStreamDestroy(b->st);
+  delete b;
+  return FK_OK;
+}
+
+extern "C" const char* fk_batch_last_error(const fk_batch* b) {
+  return b ? b->err.c_str() : "NULL batch";
+}
+
+extern "C" fk_status fk_batch_instance(const fk_batch* b, int i, fk_ctx** ctx) {
+  if (!b || !ctx || i < 0 || i >= (int)b->inst.size()) return FK_EINVAL;
+  *ctx = b->inst[i];
+  return FK_OK;
+}
+
+extern "C" fk_status fk_batch_set_chunk_bytes(fk_batch* b, double bytes) {
+  if (!b || !(bytes > 0)) return FK_EINVAL;
+  b->chunk_bytes = bytes;
+  b->dirty = true;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_batch_reset(fk_batch* b) {
+  if (!b) return FK_EINVAL;
+  b->active.clear();
+  for (int i = 0; i < (int)b->inst.size(); ++i) {
+    b->active.push_back(i);
+    b->iters[i] = 0;
+    b->delta[i] = std::numeric_limits<double>::infinity();
+  }
+  b->dirty = true;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_batch_iterate(fk_batch* b, int max_sweeps, double tol,
+                                      int use_graph, int* sweeps_out, int* iters,
+                                      double* deltas) {
+  if (!b || max_sweeps < 1) return FK_EINVAL;
+  int sweep = 0;
+  const int ninst = (int)b->inst.size();
+  std::vector<int> st;
+  std::vector<unsigned long long> keys(2 * ninst);
+  for (sweep = 0; sweep < max_sweeps && !b->active.empty(); ++sweep) {
+    if (b->dirty) {
+      const fk_status s = build_plan(b);
+      if (s != FK_OK) return s;
+    }
+    if (use_graph && !b->graph_for_plan) {
+      drop_graph(b);
+      const auto t0 = std::chrono::steady_clock::now();
+      BCHK(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+      hipError_t e = record_sweep(b);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(b->st, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return berr(b, FK_EDEVICE, "graph capture failed: %s / %s",
+                    hipGetErrorString(e), hipGetErrorString(e2));
+      }
+      b->graph = g;
+      BCHK(b, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+      b->graph_for_plan = true;
+      b->captures++;
+      b->capture_ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t0).count();
+    }
+    BCHK(b, hipEventRecord(b->ev0, b->st));
+    if (use_graph) {
+      BCHK(b, hipGraphLaunch(b->gexec, b->st));
+    } else {
+      BCHK(b, record_sweep(b));
+    }
+    BCHK(b, hipEventRecord(b->ev1, b->st));
+    st.assign(b->n_status, 0);
+    BCHK(b, hipMemcpyAsync(st.data(), b->d_status, sizeof(int) * b->n_status,
+                           hipMemcpyDeviceToHost, b->st));
+    BCHK(b, hipMemcpyAsync(keys.data(), b->d_keys, sizeof(unsigned long long) * 2 * ninst,
+                           hipMemcpyDeviceToHost, b->st));
+    BCHK(b, hipStreamSynchronize(b->st));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+    b->last_sweep_ms = ms;
+    b->total_ms += ms;
+    for (int q = 0; q < b->n_status; ++q)
+      if (st[q] != 0)
+        return berr(b, st[q] > 0 ? FK_ESINGULAR : FK_ENONFINITE,
+                    "sweep %d: inversion %d failed at column %d", sweep + 1, q,
+                    (st[q] > 0 ? st[q] : -st[q]) - 1);
+    std::vector<int> still;
+    for (int id : b->active) {
+      b->iters[id]++;
+      b->inst[id]->have_gloc = true;
+      double dg, ds;
+      std::memcpy(&dg, &keys[2 * id], sizeof dg);
+      std::memcpy(&ds, &keys[2 * id + 1], sizeof ds);
+      if (!(ds <= std::numeric_limits<double>::max()))
+        return berr(b, FK_ENONFINITE, "instance %d: non-finite Sigma", id);
+      b->delta[id] = (b->iters[id] == 1) ? std::numeric_limits<double>::infinity() : dg;
+      if (!(b->delta[id] < tol)) still.push_back(id);
+    }
+    if (still.size() != b->active.size()) {
+      b->active = still;
+      b->dirty = true;
+    }
+  }
+  if (sweeps_out) *sweeps_out = sweep;
+  for (int i = 0; i < ninst; ++i) {
+    if (iters) iters[i] = b->iters[i];
+    if (deltas) deltas[i] = b->delta[i];
+  }
+  return FK_OK;
+}
+
+extern "C" fk_status fk_batch_timings(const fk_batch* b, double* out4) {
+  if (!b || !out4) return FK_EINVAL;
+  out4[0] = b->last_sweep_ms;
+  out4[1] = b->total_ms;
+  out4[2] = b->captures;
+  out4[3] = b->capture_ms;
+  return FK_OK;
+}

@@ -1,0 +1,293 @@
+// Host-side driver pieces shared by the single-instance context and the
+// multi-instance sweep: fill kernels, the inversion batch (uniform or uneven
+// matrix sizes) and the blocked Gauss-Jordan schedule.
+#pragma once
+
+#include <algorithm>
+#include <vector>
+
+#include "fk_internal.h"
+#include "fk_kernels.h"
+
+namespace fk {
+namespace {
+
+
+__global__ void k_fill_int(int* p, int v, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+__global__ void k_fill_f64(double* p, double v, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+hipError_t fill_int(int* p, int v, size_t n, hipStream_t st) {
+  size_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_fill_int, dim3((int)g), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_u64(unsigned long long* p, unsigned long long v, int n,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u64, dim3((n + 63) / 64), dim3(64), 0, st, p, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_f64(double* p, double v, size_t n, hipStream_t st) {
+  size_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_fill_f64, dim3((int)g), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+// A batch of same-size matrices for the blocked Gauss-Jordan inversion.
+template <typename T> struct Batch {
+  int cap = 0, n = 0, ld = 0;
+  size_t stride = 0;
+  cplx<T>* x = nullptr;
+  cplx<T>* bbuf = nullptr;     // gathered pivot rows, kNBO x ld per matrix
+  int* piv = nullptr;
+  int* rowcol = nullptr;
+  int* status = nullptr;
+  MatDesc* descs = nullptr;
+  TileItem* items = nullptr;
+  // per outer step S: tile items of the next block's columns ("narrow") and of
+  // all other columns ("big"), matrix-major so a prefix serves fewer matrices
+  std::vector<int> offN, cntN, offB, cntB;
+  int nouter = 0;
+  // uneven batches (matrices of different sizes packed back to back): item
+  // totals per step, total pivot ints, and capacities of the buffers
+  bool uniform = true;
+  std::vector<int> totN, totB;
+  size_t nints = 0;
+  size_t x_cap = 0, b_cap = 0, i_cap = 0, it_cap = 0;
+  int d_cap = 0;
+  bool owns = true;   // false: x/bbuf/piv/rowcol are borrowed shared storage
+};
+
+template <typename T> void batch_free(Batch<T>& b) {
+  if (b.owns) {
+    if (b.x) (void)hipFree(b.x);
+    if (b.bbuf) (void)hipFree(b.bbuf);
+    if (b.piv) (void)hipFree(b.piv);
+    if (b.rowcol) (void)hipFree(b.rowcol);
+  }
+  if (b.status) (void)hipFree(b.status);
+  if (b.descs) (void)hipFree(b.descs);
+  if (b.items) (void)hipFree(b.items);
+  b = Batch<T>();
+}
+
+template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
+  batch_free(b);
+  b.cap = cap;
+  b.n = n;
+  b.ld = n;
+  b.stride = (size_t)n * n;
+  b.nouter = (n + kNBO - 1) / kNBO;
+  hipError_t e;
+  if ((e = hipMalloc(&b.x, sizeof(cplx<T>) * b.stride * cap)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.bbuf, sizeof(cplx<T>) * (size_t)kNBO * b.ld * cap)) != hipSuccess)
+    return e;
+  if ((e = hipMalloc(&b.piv, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.rowcol, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
+  if ((e = hipMalloc(&b.status, sizeof(int) * cap)) != hipSuccess) return e;
+  std::vector<MatDesc> d(cap);
+  for (int m = 0; m < cap; ++m) {
+    d[m].xoff = (long long)b.stride * m;
+    d[m].boff = (long long)kNBO * b.ld * m;
+    d[m].n = n;
+    d[m].ld = b.ld;
+    d[m].ioff = n * m;
+    d[m].status_idx = m;
+  }
+  if ((e = hipMalloc(&b.descs, sizeof(MatDesc) * cap)) != hipSuccess) return e;
+  if ((e = hipMemcpy(b.descs, d.data(), sizeof(MatDesc) * cap,
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  const int nt = (n + kTile - 1) / kTile;
+  std::vector<TileItem> it;
+  b.offN.assign(b.nouter, 0);
+  b.cntN.assign(b.nouter, 0);
+  b.offB.assign(b.nouter, 0);
+  b.cntB.assign(b.nouter, 0);
+  for (int S = 0; S < b.nouter; ++S) {
+    for (int pass = 0; pass < 2; ++pass) {
+      (pass ? b.offB : b.offN)[S] = (int)it.size();
+      int per = 0;
+      for (int m = 0; m < cap; ++m) {
+        per = 0;
+        for (int tc = 0; tc < nt; ++tc) {
+          const int blk = tc / (kNBO / kTile);
+          const bool narrow = blk == S + 1;
+          const bool big = blk != S && blk != S + 1;
+          if (pass == 0 ? !narrow : !big) continue;
+          for (int tr = 0; tr < nt; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
+          per += nt;
+        }
+      }
+      (pass ? b.cntB : b.cntN)[S] = per;
+    }
+  }
+  if ((e = hipMalloc(&b.items, sizeof(TileItem) * std::max<size_t>(it.size(), 1))) !=
+      hipSuccess)
+    return e;
+  if (it.empty()) return hipSuccess;
+  return hipMemcpy(b.items, it.data(), sizeof(TileItem) * it.size(),
+                   hipMemcpyHostToDevice);
+}
+
+template <typename P> hipError_t grow(P** ptr, size_t* cap, size_t want) {
+  if (*ptr && *cap >= want) return hipSuccess;
+  if (*ptr) (void)hipFree(*ptr);
+  *ptr = nullptr;
+  *cap = 0;
+  hipError_t e = hipMalloc(ptr, sizeof(P) * std::max<size_t>(want, 1));
+  if (e == hipSuccess) *cap = want;
+  return e;
+}
+
+// Configure the batch for matrices of sizes n[m] (ld = n[m]) packed back to
+// back.  status_idx[m] is the slot of matrix m in the status array passed to
+// batch_invert (the caller zeroes it).  Buffers grow as needed and are kept.
+template <typename T>
+hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
+                              const std::vector<int>& status_idx) {
+  const int nm = (int)n.size();
+  b.uniform = false;
+  b.cap = nm;
+  b.n = 0;
+  b.ld = 0;
+  b.stride = 0;
+  std::vector<MatDesc> d(nm);
+  size_t xo = 0, bo = 0, io = 0;
+  int nouter = 0;
+  for (int m = 0; m < nm; ++m) {
+    d[m].xoff = (long long)xo;
+    d[m].boff = (long long)bo;
+    d[m].n = n[m];
+    d[m].ld = n[m];
+    d[m].ioff = (int)io;
+    d[m].status_idx = status_idx[m];
+    xo += (size_t)n[m] * n[m];
+    bo += (size_t)kNBO * n[m];
+    io += (size_t)n[m];
+    nouter = std::max(nouter, (n[m] + kNBO - 1) / kNBO);
+  }
+  b.nouter = nouter;
+  b.nints = io;
+  hipError_t e;
+  if ((e = grow(&b.x, &b.x_cap, xo)) != hipSuccess) return e;
+  if ((e = grow(&b.bbuf, &b.b_cap, bo)) != hipSuccess) return e;
+  size_t ic = b.i_cap;
+  if ((e = grow(&b.piv, &ic, io)) != hipSuccess) return e;
+  ic = b.i_cap;
+  if ((e = grow(&b.rowcol, &ic, io)) != hipSuccess) return e;
+  b.i_cap = std::max(b.i_cap, io);
+  size_t dc = (size_t)b.d_cap;
+  if ((e = grow(&b.descs, &dc, (size_t)nm)) != hipSuccess) return e;
+  b.d_cap = (int)dc;
+  if ((e = hipMemcpy(b.descs, d.data(), sizeof(MatDesc) * nm,
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  std::vector<TileItem> it;
+  b.offN.assign(nouter, 0);
+  b.offB.assign(nouter, 0);
+  b.totN.assign(nouter, 0);
+  b.totB.assign(nouter, 0);
+  for (int S = 0; S < nouter; ++S) {
+    for (int pass = 0; pass < 2; ++pass) {
+      (pass ? b.offB : b.offN)[S] = (int)it.size();
+      for (int m = 0; m < nm; ++m) {
+        if (S * kNBO >= n[m]) continue;
+        const int nt = (n[m] + kTile - 1) / kTile;
+        for (int tc = 0; tc < nt; ++tc) {
+          const int blk = tc / (kNBO / kTile);
+          const bool narrow = blk == S + 1;
+          const bool big = blk != S && blk != S + 1;
+          if (pass == 0 ? !narrow : !big) continue;
+          for (int tr = 0; tr < nt; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
+        }
+      }
+      (pass ? b.totB : b.totN)[S] = (int)it.size() - (pass ? b.offB : b.offN)[S];
+    }
+  }
+  if ((e = grow(&b.items, &b.it_cap, it.size())) != hipSuccess) return e;
+  if (it.empty()) return hipSuccess;
+  return hipMemcpy(b.items, it.data(), sizeof(TileItem) * it.size(),
+                   hipMemcpyHostToDevice);
+}
+
+// Side stream and events of the look-ahead (default priority).
+struct Aux {
+  hipStream_t st2 = nullptr;
+  hipEvent_t evN = nullptr, evP = nullptr;
+  bool lookahead = false;  // factor the next block on st2 (else in order on st)
+};
+
+// Invert matrices 0..nmat-1 of the batch in place (permuted storage).  The
+// next outer block is factored on the side stream while the big update of
+// the current block runs on st.  ev_steps (nullable) brackets the kernels.
+// For an uneven batch nmat must be b.cap and status is the caller's array
+// (indexed by the descriptors' status_idx, not cleared here).
+template <typename T>
+hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
+                        int* launches, hipEvent_t* ev_steps = nullptr,
+                        int* status = nullptr) {
+  hipError_t e;
+  int* stat = status ? status : b.status;
+  const size_t nints = b.uniform ? (size_t)b.n * nmat : b.nints;
+  if ((e = fill_int(b.rowcol, -1, nints, st)) != hipSuccess) return e;
+  if (!status && (e = fill_int(b.status, 0, (size_t)nmat, st)) != hipSuccess) return e;
+  if (ev_steps && (e = hipEventRecord(ev_steps[0], st)) != hipSuccess) return e;
+  int nl = 0;
+  if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, 0, stat, st)) !=
+      hipSuccess)
+    return e;
+  ++nl;
+  for (int S = 0; S < b.nouter; ++S) {
+    const bool next = S + 1 < b.nouter;
+    if ((e = gje_gather<T>(b.x, b.bbuf, b.piv, b.descs, nmat, S, st)) != hipSuccess)
+      return e;
+    ++nl;
+    if (next) {
+      const int nN = b.uniform ? nmat * b.cntN[S] : b.totN[S];
+      if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offN[S],
+                             nN, S, st)) != hipSuccess)
+        return e;
+      ++nl;
+      hipStream_t ps = ax.lookahead ? ax.st2 : st;
+      if (ax.lookahead) {
+        if ((e = hipEventRecord(ax.evN, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ax.st2, ax.evN, 0)) != hipSuccess) return e;
+      }
+      if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, S + 1, stat,
+                            ps)) != hipSuccess)
+        return e;
+      ++nl;
+      if (ax.lookahead && (e = hipEventRecord(ax.evP, ax.st2)) != hipSuccess) return e;
+    }
+    const int nB = b.uniform ? nmat * b.cntB[S] : b.totB[S];
+    if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offB[S],
+                           nB, S, st)) != hipSuccess)
+      return e;
+    ++nl;
+    if (next && ax.lookahead && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess)
+      return e;
+  }
+  if (ev_steps && (e = hipEventRecord(ev_steps[1], st)) != hipSuccess) return e;
+  if (launches) *launches += nl;
+  return hipSuccess;
+}
+
+
+}  // namespace
+}  // namespace fk

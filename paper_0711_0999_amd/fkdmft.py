@@ -69,6 +69,16 @@ SIGNATURES = {
                                   _ip, _dp, _dp]),
     "fk_set_switch": (ctypes.c_int, [_vp, ctypes.c_double]),
     "fk_timings": (ctypes.c_int, [_vp, _dp]),
+    "fk_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Contour),
+                                       ctypes.POINTER(Model), ctypes.POINTER(_vp)]),
+    "fk_batch_destroy": (ctypes.c_int, [_vp]),
+    "fk_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "fk_batch_instance": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "fk_batch_set_chunk_bytes": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "fk_batch_reset": (ctypes.c_int, [_vp]),
+    "fk_batch_iterate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                        _ip, _ip, _dp]),
+    "fk_batch_timings": (ctypes.c_int, [_vp, _dp]),
 }
 
 _lib = None
@@ -266,3 +276,93 @@ class Context:
         return dict(build_ms=out[0], invert_ms=out[1], refine_ms=out[2],
                     reduce_ms=out[3], impurity_ms=out[4], launches=int(out[5]),
                     step_kernels_ms=out[6])
+
+
+class _Instance(Context):
+    """View of one instance of a Batch (owned by the batch)."""
+
+    def __init__(self, lib, handle, owner):
+        self._lib = lib
+        self._h = handle
+        self._owner = owner
+        nt, ntau, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lib.fk_dims(handle, ctypes.byref(nt), ctypes.byref(ntau), ctypes.byref(nc))
+        self.n_t, self.n_tau, self.n_c = nt.value, ntau.value, nc.value
+
+    def close(self):
+        self._h = None
+
+
+class Batch:
+    """fk_batch: instances = list of dicts with the keyword arguments of
+    Context (contour, model); instance(i) gives a Context-like view."""
+
+    def __init__(self, instances):
+        lib = library()
+        self._lib = lib
+        n = len(instances)
+        cs = (Contour * n)()
+        ms = (Model * n)()
+        for i, kw in enumerate(instances):
+            cs[i] = Contour(kw["t_min"], kw["t_max"], kw["dt"], kw["dtau"], kw["beta"])
+            ms[i] = Model(kw["U"], kw["E"], kw.get("mu", 0.0), kw.get("w1", 0.5),
+                          kw.get("n_eps", 10), kw.get("n_ebar", 10),
+                          CONVENTION[kw.get("convention", "symmetric")], 0)
+        h = _vp()
+        s = lib.fk_batch_create(n, cs, ms, ctypes.byref(h))
+        if s != FK_OK:
+            raise FkError(s, "fk_batch_create")
+        self._h = h
+        self.n = n
+        self._views = []
+        for i in range(n):
+            c = _vp()
+            self._check(lib.fk_batch_instance(h, i, ctypes.byref(c)), "fk_batch_instance")
+            self._views.append(_Instance(lib, c, self))
+
+    def _check(self, s, what):
+        if s != FK_OK:
+            raise FkError(s, f"{what}: {self._lib.fk_batch_last_error(self._h).decode()}")
+
+    def instance(self, i):
+        return self._views[i]
+
+    def set_chunk_bytes(self, b):
+        self._check(self._lib.fk_batch_set_chunk_bytes(self._h, float(b)), "chunk")
+
+    def reset(self):
+        self._check(self._lib.fk_batch_reset(self._h), "fk_batch_reset")
+
+    def iterate(self, max_sweeps, tol=0.0, use_graph=True):
+        sw = ctypes.c_int()
+        it = (ctypes.c_int * self.n)()
+        dl = np.zeros(self.n)
+        self._check(self._lib.fk_batch_iterate(self._h, max_sweeps, tol, int(use_graph),
+                                               ctypes.byref(sw), it, _dptr(dl)),
+                    "fk_batch_iterate")
+        return dict(sweeps=sw.value, iters=np.array(list(it)), deltas=dl)
+
+    def timings(self):
+        out = np.zeros(4)
+        self._check(self._lib.fk_batch_timings(self._h, _dptr(out)), "fk_batch_timings")
+        return dict(last_sweep_ms=out[0], total_ms=out[1], captures=int(out[2]),
+                    capture_ms=out[3])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for v in self._views:
+                v._h = None
+            self._lib.fk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
