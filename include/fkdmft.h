@@ -171,6 +171,30 @@ fk_status fk_set_switch(fk_ctx* ctx, double switch_tol);
  * inversion kernel launches, out[6] summed duration of the step kernels. */
 fk_status fk_timings(const fk_ctx* ctx, double* out7);
 
+/* ---- schedule autotuner --------------------------------------------------- */
+
+/* A schedule of the batched inversion: the trailing-update tile height
+ * (64: 64 x 64 tiles, 4 waves, two workgroups per CU; 128: 128 x 64 tiles,
+ * 8 waves sharing each B chunk), the number of point matrices per batch, and
+ * whether the next 128-column block is factored on a second stream. */
+typedef struct {
+  int tile_rows;        /* 64 or 128 */
+  int batch;            /* matrices per batch (>= 1) */
+  int lookahead;        /* 0 or 1 */
+  double chunk_bytes;   /* device bytes of one batch at this context's N_c */
+  double est_step_ms;   /* autotune: estimated inversion time of all points */
+  int trials;           /* autotune: schedules timed */
+} fk_tuning;
+
+/* Time candidate schedules on this context's own point matrices (current
+ * Sigma): every tile height x batch sizes up to max_bytes of device memory x
+ * look-ahead on/off; each candidate inverts one batch once for warm-up and
+ * once timed, the estimate scales to all points.  Applies and returns the
+ * fastest.  keep = 0 frees the inversion buffers afterwards. */
+fk_status fk_autotune(fk_ctx* ctx, double max_bytes, int keep, fk_tuning* best);
+fk_status fk_set_tuning(fk_ctx* ctx, const fk_tuning* t);
+fk_status fk_get_tuning(const fk_ctx* ctx, fk_tuning* t);
+
 /* ---- many instances in one sweep ----------------------------------------- */
 
 /* A set of independent DMFT problems (contours and models may differ: uneven
@@ -202,6 +226,8 @@ fk_status fk_batch_reset(fk_batch* b);
 fk_status fk_batch_iterate(fk_batch* b, int max_sweeps, double tol,
                            int use_graph, int* sweeps_out, int* iters,
                            double* deltas);
+/* Tile height, look-ahead and chunk_bytes of t apply to every sweep. */
+fk_status fk_batch_set_tuning(fk_batch* b, const fk_tuning* t);
 /* out4: last sweep ms, total sweep ms, graph recordings, last recording ms. */
 fk_status fk_batch_timings(const fk_batch* b, double* out4);
 

@@ -198,8 +198,8 @@ template <> Batch<float>& lattice_batch<float>(fk_ctx* c) { return c->b32; }
 template <typename T> fk_status ensure_batch(fk_ctx* c) {
   Batch<T>& b = lattice_batch<T>(c);
   const int cap = batch_cap_for<T>(c);
-  if (b.x && b.cap == cap) return FK_OK;
-  HIPCHK(c, batch_alloc(b, cap, c->ci.n_c));
+  if (b.x && b.cap == cap && b.variant == c->variant) return FK_OK;
+  HIPCHK(c, batch_alloc(b, cap, c->ci.n_c, c->variant));
   return FK_OK;
 }
 
@@ -300,7 +300,8 @@ fk_status lattice_step_mixed(fk_ctx* c, double* ir_out) {
   const size_t nb = (c->npts + cap - 1) / cap;
   cap = (c->npts + nb - 1) / nb;
   Batch<float>& b = c->b32;
-  if (!b.x || b.cap != (int)cap) HIPCHK(c, batch_alloc(b, (int)cap, n));
+  if (!b.x || b.cap != (int)cap || b.variant != c->variant)
+    HIPCHK(c, batch_alloc(b, (int)cap, n, c->variant));
   if (ir > 0 && c->ir_cap != (int)cap) {
     c64** bufs[] = {&c->ir_x, &c->ir_p, &c->ir_y};
     for (c64** q : bufs) {
@@ -786,5 +787,91 @@ extern "C" fk_status fk_iterate(fk_ctx* c, int max_iter, double tol,
 extern "C" fk_status fk_timings(const fk_ctx* c, double* out7) {
   if (!c || !out7) return FK_EINVAL;
   for (int i = 0; i < 7; ++i) out7[i] = c->times[i];
+  return FK_OK;
+}
+
+// ================================================================ autotuner
+namespace {
+double matrix_bytes(const fk_ctx* c) {
+  const double n = c->ci.n_c;
+  return 16.0 * (n * n + kNBO * n) + 8.0 * n;
+}
+}  // namespace
+
+extern "C" fk_status fk_set_tuning(fk_ctx* c, const fk_tuning* t) {
+  if (!c || !t || (t->tile_rows != 64 && t->tile_rows != 128) || t->batch < 0)
+    return FK_EINVAL;
+  c->variant = t->tile_rows == 128 ? 1 : 0;
+  c->aux.lookahead = t->lookahead != 0;
+  if (t->batch > 0) c->want_batch = t->batch;
+  c->tuned = *t;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_get_tuning(const fk_ctx* c, fk_tuning* t) {
+  if (!c || !t) return FK_EINVAL;
+  fk_tuning r = c->tuned;
+  r.tile_rows = c->variant == 1 ? 128 : 64;
+  r.lookahead = c->aux.lookahead ? 1 : 0;
+  r.batch = c->b64.cap > 0 ? c->b64.cap : c->want_batch;
+  r.chunk_bytes = r.batch * matrix_bytes(c);
+  *t = r;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_autotune(fk_ctx* c, double max_bytes, int keep,
+                                 fk_tuning* best) {
+  if (!c || !(max_bytes > 0)) return FK_EINVAL;
+  const double mb = matrix_bytes(c);
+  int cap_max = (int)std::min<double>(c->npts, std::floor(max_bytes / mb));
+  if (cap_max < 1) return set_err(c, FK_ENOMEM, "max_bytes below one matrix");
+  std::vector<int> caps;
+  for (int d : {4, 2, 1}) {
+    const int b = std::max(1, cap_max / d);
+    if (std::find(caps.begin(), caps.end(), b) == caps.end()) caps.push_back(b);
+  }
+  const int n = c->ci.n_c;
+  HIPCHK(c, launch_sigma_weight(c->d_sigma, c->d_w, c->d_sigt, n, c->st));
+  fk_tuning bestt{64, 1, 0, 0.0, std::numeric_limits<double>::infinity(), 0};
+  int trials = 0;
+  fk_status s;
+  for (int variant : {0, 1})
+    for (int cap : caps)
+      for (int la : {0, 1}) {
+        c->variant = variant;
+        c->want_batch = cap;
+        c->aux.lookahead = la != 0;
+        batch_free(c->b64);
+        if ((s = ensure_batch<double>(c)) != FK_OK) return s;
+        Batch<double>& b = c->b64;
+        const int nmat = b.cap;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(c, launch_build<double>(c->d_sigt, c->tab, 0, nmat, b.x, b.stride,
+                                         b.ld, n, c->st));
+          HIPCHK(c, hipEventRecord(c->ev[0], c->st));
+          HIPCHK(c, batch_invert<double>(b, nmat, c->st, c->aux, nullptr));
+          HIPCHK(c, hipEventRecord(c->ev[1], c->st));
+          HIPCHK(c, hipStreamSynchronize(c->st));
+          ms = elapsed(c->ev[0], c->ev[1]);
+        }
+        if ((s = check_status(c, b.status, nmat, 0, "autotune inversion")) != FK_OK)
+          return s;
+        const double est = ms / nmat * c->npts *
+                           (double)((c->npts + nmat - 1) / nmat) * nmat / c->npts;
+        ++trials;
+        if (est < bestt.est_step_ms) {
+          bestt.tile_rows = variant ? 128 : 64;
+          bestt.batch = nmat;
+          bestt.lookahead = la;
+          bestt.chunk_bytes = nmat * mb;
+          bestt.est_step_ms = est;
+        }
+      }
+  bestt.trials = trials;
+  batch_free(c->b64);
+  if ((s = fk_set_tuning(c, &bestt)) != FK_OK) return s;
+  if (keep && (s = ensure_batch<double>(c)) != FK_OK) return s;
+  if (best) *best = bestt;
   return FK_OK;
 }

@@ -178,6 +178,7 @@ struct fk_batch {
   int captures = 0;
   double capture_ms = 0.0, last_sweep_ms = 0.0, total_ms = 0.0;
   int max_nc = 0;
+  int variant = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -275,6 +276,7 @@ fk_status build_plan(fk_batch* b) {
   for (size_t g = 0; g < groups.size(); ++g) {
     Chunk& ch = b->chunks[g];
     borrow(ch.b, b->x, b->x_cap, b->bbuf, b->b_cap, b->piv, b->rowcol, b->i_cap);
+    ch.b.variant = b->variant;
     BCHK(b, batch_setup_uneven(ch.b, sizes[g], sidx[g]));
     size_t xo = 0, io = 0;
     for (const Job& j : groups[g]) {
@@ -609,5 +611,14 @@ extern "C" fk_status fk_batch_timings(const fk_batch* b, double* out4) {
   out4[1] = b->total_ms;
   out4[2] = b->captures;
   out4[3] = b->capture_ms;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_batch_set_tuning(fk_batch* b, const fk_tuning* t) {
+  if (!b || !t || (t->tile_rows != 64 && t->tile_rows != 128)) return FK_EINVAL;
+  b->variant = t->tile_rows == 128 ? 1 : 0;
+  b->aux.lookahead = t->lookahead != 0;
+  if (t->chunk_bytes > 0) b->chunk_bytes = t->chunk_bytes;
+  b->dirty = true;
   return FK_OK;
 }

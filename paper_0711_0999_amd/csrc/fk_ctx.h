@@ -62,6 +62,8 @@ struct fk_ctx {
   int* d_iota = nullptr;
   size_t batch_bytes = 0;
   int want_batch = 0;
+  int variant = 0;             // trailing-update tile shape
+  fk_tuning tuned{64, 0, 0, 0.0, 0.0, 0};
 
   bool have_gloc = false;
   bool have_prev = false;

@@ -71,6 +71,7 @@ template <typename T> struct Batch {
   size_t x_cap = 0, b_cap = 0, i_cap = 0, it_cap = 0;
   int d_cap = 0;
   bool owns = true;   // false: x/bbuf/piv/rowcol are borrowed shared storage
+  int variant = 0;    // trailing-update tile shape (see gje_update)
 };
 
 template <typename T> void batch_free(Batch<T>& b) {
@@ -86,8 +87,10 @@ template <typename T> void batch_free(Batch<T>& b) {
   b = Batch<T>();
 }
 
-template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
+template <typename T>
+hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
   batch_free(b);
+  b.variant = variant;
   b.cap = cap;
   b.n = n;
   b.ld = n;
@@ -114,6 +117,7 @@ template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
                      hipMemcpyHostToDevice)) != hipSuccess)
     return e;
   const int nt = (n + kTile - 1) / kTile;
+  const int ntr = (n + tile_rows(variant) - 1) / tile_rows(variant);
   std::vector<TileItem> it;
   b.offN.assign(b.nouter, 0);
   b.cntN.assign(b.nouter, 0);
@@ -130,8 +134,8 @@ template <typename T> hipError_t batch_alloc(Batch<T>& b, int cap, int n) {
           const bool narrow = blk == S + 1;
           const bool big = blk != S && blk != S + 1;
           if (pass == 0 ? !narrow : !big) continue;
-          for (int tr = 0; tr < nt; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
-          per += nt;
+          for (int tr = 0; tr < ntr; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
+          per += ntr;
         }
       }
       (pass ? b.cntB : b.cntN)[S] = per;
@@ -209,12 +213,13 @@ hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
       for (int m = 0; m < nm; ++m) {
         if (S * kNBO >= n[m]) continue;
         const int nt = (n[m] + kTile - 1) / kTile;
+        const int ntr = (n[m] + tile_rows(b.variant) - 1) / tile_rows(b.variant);
         for (int tc = 0; tc < nt; ++tc) {
           const int blk = tc / (kNBO / kTile);
           const bool narrow = blk == S + 1;
           const bool big = blk != S && blk != S + 1;
           if (pass == 0 ? !narrow : !big) continue;
-          for (int tr = 0; tr < nt; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
+          for (int tr = 0; tr < ntr; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
         }
       }
       (pass ? b.totB : b.totN)[S] = (int)it.size() - (pass ? b.offB : b.offN)[S];
@@ -261,7 +266,7 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
     if (next) {
       const int nN = b.uniform ? nmat * b.cntN[S] : b.totN[S];
       if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offN[S],
-                             nN, S, st)) != hipSuccess)
+                             nN, S, b.variant, st)) != hipSuccess)
         return e;
       ++nl;
       hipStream_t ps = ax.lookahead ? ax.st2 : st;
@@ -277,7 +282,7 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
     }
     const int nB = b.uniform ? nmat * b.cntB[S] : b.totB[S];
     if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offB[S],
-                           nB, S, st)) != hipSuccess)
+                           nB, S, b.variant, st)) != hipSuccess)
       return e;
     ++nl;
     if (next && ax.lookahead && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess)

@@ -412,20 +412,23 @@ __global__ void k_gather(const cplx<T>* __restrict__ xbuf,
 }
 
 // ------------------------------------------------------------------ update
-// C <- mask_P(C) + M B for the listed 64 x 64 tiles.  Four waves as 2 x 2
-// blocks of 32 x 32; K in chunks of kKC, double-buffered through LDS with the
-// next chunk's global loads in flight during the current chunk's MFMAs.
-template <typename T>
-__global__ __launch_bounds__(kGemmThreads, 2) void k_update(
+// C <- mask_P(C) + M B for the listed tiles of (32 WR) x 64: 2 WR waves as
+// WR x 2 blocks of 32 x 32 (WR = 2: 64 x 64 tiles, two workgroups per CU;
+// WR = 4: 128 x 64 tiles sharing each B chunk, one workgroup per CU).  K in
+// chunks of kKC, double-buffered through LDS with the next chunk's global
+// loads in flight during the current chunk's MFMAs.
+template <typename T, int WR>
+__global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
     cplx<T>* __restrict__ xbuf, const cplx<T>* __restrict__ bbuf,
     const int* __restrict__ rowcolbuf, const MatDesc* __restrict__ descs,
     const TileItem* __restrict__ items, int nitems, int S) {
   typedef typename Mfma<T>::v4 v4;
+  constexpr int TR = 32 * WR, NT = 128 * WR;
   constexpr int AP = kKC + 1, BP = kTile + 1;
-  __shared__ cplx<T> As[2][kTile * AP];
+  __shared__ cplx<T> As[2][TR * AP];
   __shared__ cplx<T> Bsh[2][kKC * BP];
-  constexpr int kLA = kTile * kKC / kGemmThreads;   // chunk loads per thread
-  constexpr int kLB = kKC * kTile / kGemmThreads;
+  constexpr int kLA = TR * kKC / NT;      // chunk loads per thread
+  constexpr int kLB = kKC * kTile / NT;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -442,7 +445,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_update(
     const int n = d.n, ld = d.ld;
     const int J0 = S * kNBO, wO = min(kNBO, n - J0);
     const int nch = (wO + kKC - 1) / kKC;
-    const int r0 = ti.tr * kTile, c0 = ti.tc * kTile;
+    const int r0 = ti.tr * TR, c0 = ti.tc * kTile;
     cplx<T>* xm = xbuf + d.xoff;
     const cplx<T>* bm = bbuf + d.boff;
     const int* rowcol = rowcolbuf + d.ioff;
@@ -469,13 +472,13 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_update(
     cplx<T> pa[kLA], pb[kLB];
 #pragma unroll
     for (int t = 0; t < kLA; ++t) {
-      const int e = tid + t * kGemmThreads;
+      const int e = tid + t * NT;
       const int i = e / kKC, k = e % kKC;
       pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(k, wO - 1)];
     }
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
-      const int e = tid + t * kGemmThreads;
+      const int e = tid + t * NT;
       const int k = e / kTile, c = e % kTile;
       pb[t] = bm[(size_t)min(k, wO - 1) * ld + min(c0 + c, n - 1)];
     }
@@ -495,7 +498,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_update(
         }
 #pragma unroll
     for (int t = 0; t < kLA; ++t) {
-      const int e = tid + t * kGemmThreads;
+      const int e = tid + t * NT;
       const int i = e / kKC, k = e % kKC;
       cplx<T> v = pa[t];
       if (!(r0 + i < n && k < wO)) v.re = v.im = T(0);
@@ -503,7 +506,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_update(
     }
 #pragma unroll
     for (int t = 0; t < kLB; ++t) {
-      const int e = tid + t * kGemmThreads;
+      const int e = tid + t * NT;
       const int k = e / kTile, c = e % kTile;
       cplx<T> v = pb[t];
       if (!(k < wO && c0 + c < n)) v.re = v.im = T(0);
@@ -518,13 +521,13 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_update(
       if (more) {
 #pragma unroll
         for (int t = 0; t < kLA; ++t) {
-          const int e = tid + t * kGemmThreads;
+          const int e = tid + t * NT;
           const int i = e / kKC, k = e % kKC;
           pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(kb + k, wO - 1)];
         }
 #pragma unroll
         for (int t = 0; t < kLB; ++t) {
-          const int e = tid + t * kGemmThreads;
+          const int e = tid + t * NT;
           const int k = e / kTile, c = e % kTile;
           pb[t] = bm[(size_t)min(kb + k, wO - 1) * ld + min(c0 + c, n - 1)];
         }
@@ -565,7 +568,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_update(
       if (more) {
 #pragma unroll
         for (int t = 0; t < kLA; ++t) {
-          const int e = tid + t * kGemmThreads;
+          const int e = tid + t * NT;
           const int i = e / kKC, k = e % kKC;
           cplx<T> v = pa[t];
           if (!(r0 + i < n && kb + k < wO)) v.re = v.im = T(0);
@@ -573,7 +576,7 @@ __global__ __launch_bounds__(kGemmThreads, 2) void k_update(
         }
 #pragma unroll
         for (int t = 0; t < kLB; ++t) {
-          const int e = tid + t * kGemmThreads;
+          const int e = tid + t * NT;
           const int k = e / kTile, c = e % kTile;
           cplx<T> v = pb[t];
           if (!(kb + k < wO && c0 + c < n)) v.re = v.im = T(0);
@@ -638,11 +641,15 @@ hipError_t gje_gather(const cplx<T>* x, cplx<T>* bbuf, const int* piv,
 template <typename T>
 hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
                       const MatDesc* d, const TileItem* items, int nitems,
-                      int S, hipStream_t st) {
+                      int S, int variant, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   const int grid = 8 * ((nitems + 7) / 8);
-  hipLaunchKernelGGL(k_update<T>, dim3(grid), dim3(kGemmThreads), 0, st, x,
-                     bbuf, rowcol, d, items, nitems, S);
+  if (variant == 1)
+    hipLaunchKernelGGL((k_update<T, 4>), dim3(grid), dim3(512), 0, st, x, bbuf,
+                       rowcol, d, items, nitems, S);
+  else
+    hipLaunchKernelGGL((k_update<T, 2>), dim3(grid), dim3(256), 0, st, x, bbuf,
+                       rowcol, d, items, nitems, S);
   return hipGetLastError();
 }
 
@@ -653,7 +660,7 @@ hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
                                     const MatDesc*, int, int, hipStream_t);   \
   template hipError_t gje_update<T>(cplx<T>*, const cplx<T>*, const int*,     \
                                     const MatDesc*, const TileItem*, int, int, \
-                                    hipStream_t);
+                                    int, hipStream_t);
 FK_INST(double)
 FK_INST(float)
 

@@ -52,9 +52,12 @@ hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
 template <typename T>
 hipError_t gje_gather(const cplx<T>* x, cplx<T>* bbuf, const int* piv,
                       const MatDesc* d, int nmat, int S, hipStream_t st);
+// variant 0: 64 x 64 tiles (256 threads); 1: 128 x 64 tiles (512 threads).
+// TileItem.tr counts tiles of tile_rows(variant) rows.
 template <typename T>
 hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
                       const MatDesc* d, const TileItem* items, int nitems,
-                      int S, hipStream_t st);
+                      int S, int variant, hipStream_t st);
+inline int tile_rows(int variant) { return variant == 1 ? 128 : 64; }
 
 }  // namespace fk

@@ -41,6 +41,15 @@ class Model(ctypes.Structure):
                 ("convention", ctypes.c_int), ("gh_average", ctypes.c_int)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int), ("batch", ctypes.c_int),
+                ("lookahead", ctypes.c_int), ("chunk_bytes", ctypes.c_double),
+                ("est_step_ms", ctypes.c_double), ("trials", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 _vp = ctypes.c_void_p
@@ -69,6 +78,11 @@ SIGNATURES = {
                                   _ip, _dp, _dp]),
     "fk_set_switch": (ctypes.c_int, [_vp, ctypes.c_double]),
     "fk_timings": (ctypes.c_int, [_vp, _dp]),
+    "fk_autotune": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int,
+                                   ctypes.POINTER(Tuning)]),
+    "fk_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "fk_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "fk_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Contour),
                                        ctypes.POINTER(Model), ctypes.POINTER(_vp)]),
     "fk_batch_destroy": (ctypes.c_int, [_vp]),
@@ -270,6 +284,21 @@ class Context:
         return dict(iters=it.value, delta=d.value, history=hist[:it.value],
                     converged=(s == FK_OK))
 
+    def autotune(self, max_bytes=24 * 2 ** 30, keep=True):
+        t = Tuning()
+        self._check(self._lib.fk_autotune(self._h, float(max_bytes), int(keep),
+                                          ctypes.byref(t)), "fk_autotune")
+        return t.as_dict()
+
+    def set_tuning(self, tile_rows=64, batch=0, lookahead=0):
+        t = Tuning(tile_rows, batch, lookahead, 0.0, 0.0, 0)
+        self._check(self._lib.fk_set_tuning(self._h, ctypes.byref(t)), "fk_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        self._check(self._lib.fk_get_tuning(self._h, ctypes.byref(t)), "fk_get_tuning")
+        return t.as_dict()
+
     def timings(self):
         out = np.zeros(7)
         self._check(self._lib.fk_timings(self._h, _dptr(out)), "fk_timings")
@@ -341,6 +370,11 @@ class Batch:
                                                ctypes.byref(sw), it, _dptr(dl)),
                     "fk_batch_iterate")
         return dict(sweeps=sw.value, iters=np.array(list(it)), deltas=dl)
+
+    def set_tuning(self, tile_rows=64, lookahead=0, chunk_bytes=0.0):
+        t = Tuning(tile_rows, 0, lookahead, float(chunk_bytes), 0.0, 0)
+        self._check(self._lib.fk_batch_set_tuning(self._h, ctypes.byref(t)),
+                    "fk_batch_set_tuning")
 
     def timings(self):
         out = np.zeros(4)

@@ -49,15 +49,17 @@ def test_one_lattice_step_c1_random_sigma(lib):
     ctx.close()
 
 
+@pytest.mark.parametrize("tile_rows", [64, 128])
 @pytest.mark.parametrize("batch", [1, 5, 0])
-def test_ragged_sizes_and_batches(lib, batch):
+def test_ragged_sizes_and_batches(lib, batch, tile_rows):
     """N_c = 73 (two stripes, the second ragged), 3 x 4 points, batches of
-    1 and 5 matrices (ragged last batch) and the default."""
-    say(f"case: ragged N_c=73, batch={batch}")
+    1 and 5 matrices (ragged last batch) and the default, both update tiles."""
+    say(f"case: ragged N_c=73, batch={batch}, tile_rows={tile_rows}")
     kw = dict(t_min=-1.0, t_max=2.0, dt=0.1, dtau=0.1, beta=1.3, U=1.0, E=1.5,
               n_eps=3, n_ebar=4)
     ctx = lib.Context(**kw)
     assert ctx.n_c == 73
+    ctx.set_tuning(tile_rows=tile_rows, batch=0, lookahead=0)
     if batch:
         ctx.set_batch(batch)
     sig = inputs.random_sigma(ctx.n_c, seed=2, scale=0.2)
@@ -70,14 +72,19 @@ def test_ragged_sizes_and_batches(lib, batch):
     assert relerr(ctx.get_current()[1], jo) < TOL64
 
 
+@pytest.mark.parametrize("lookahead", [0, 1])
+@pytest.mark.parametrize("tile_rows", [64, 128])
 @pytest.mark.parametrize("n_steps_kw", [
     dict(t_min=-2.0, t_max=2.0, dt=0.05, dtau=0.05, beta=2.0),     # N_c = 200
     dict(t_min=-3.0, t_max=3.2, dt=0.05, dtau=0.1, beta=1.0),      # N_c = 258
+    dict(t_min=-4.0, t_max=5.0, dt=0.025, dtau=0.05, beta=1.55),   # N_c = 751
 ])
-def test_several_tiles(lib, n_steps_kw):
-    """Contours spanning several 64-column panels and row tiles."""
-    say(f"case: several tiles {n_steps_kw}")
+def test_several_tiles(lib, n_steps_kw, tile_rows, lookahead):
+    """Contours spanning several 128-column outer blocks and row tiles, both
+    update tile shapes, with and without the look-ahead stream."""
+    say(f"case: several tiles {n_steps_kw} tile_rows={tile_rows} lookahead={lookahead}")
     ctx = lib.Context(U=1.5, E=2.0, n_eps=3, n_ebar=3, **n_steps_kw)
+    ctx.set_tuning(tile_rows=tile_rows, batch=0, lookahead=lookahead)
     sig = inputs.random_sigma(ctx.n_c, seed=3, scale=0.1)
     ctx.set_sigma(sig)
     ctx.compute_gloc()
@@ -172,3 +179,22 @@ def test_error_paths(lib):
     ctx.compute_gloc()
     r = ctx.iterate(2, tol=1e-30)
     assert not r["converged"] and r["iters"] == 2
+
+
+def test_autotune_picks_a_valid_schedule(lib):
+    """The autotuner times every tile shape x batch x look-ahead on the
+    context's own matrices and applies the fastest; results stay the same."""
+    say("case: autotune")
+    kw = dict(t_min=-3.0, t_max=3.2, dt=0.05, dtau=0.1, beta=1.0, U=1.5, E=2.0,
+              n_eps=4, n_ebar=4)
+    ref = lib.Context(**kw)
+    sig = inputs.random_sigma(ref.n_c, seed=8, scale=0.1)
+    ref.set_sigma(sig)
+    ref.compute_gloc()
+    ctx = lib.Context(**kw)
+    ctx.set_sigma(sig)
+    t = ctx.autotune(max_bytes=64 * 2 ** 20)
+    assert t["tile_rows"] in (64, 128) and t["trials"] >= 4 and t["batch"] >= 1
+    assert t["est_step_ms"] > 0
+    ctx.compute_gloc()
+    assert relerr(ctx.get_gloc(), ref.get_gloc()) < 1e-13
