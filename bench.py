@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--converge", action="store_true")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-bytes", type=float, default=48 * 2 ** 30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not "
@@ -91,8 +94,14 @@ def main():
     stream = torch.cuda.current_stream()
     w = configs.c2(args.U) if args.workload == "c2" else configs.C1
     ctx = fkdmft.Context(stream=stream, **w.kwargs())
+    tuning = None
     if args.batch:
         ctx.set_batch(args.batch)
+    elif not args.no_autotune:
+        t0 = time.perf_counter()
+        tuning = ctx.autotune(max_bytes=args.tune_bytes)
+        tuning["seconds"] = time.perf_counter() - t0
+        log(f"bench: autotune picked {tuning}")
     n, npts = ctx.n_c, w.n_eps * w.n_ebar
     prec = fkdmft.FK_MIXED if args.mixed else fkdmft.FK_FP64
     log(f"bench: workload {w.name} N_c={n} points={npts} steps={args.steps} "
@@ -146,19 +155,60 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "gje_step_kernel",
+                     "kernel": "inversion (k_outer_panel + k_gather + k_update)",
                      "flops_per_launch": flops_iter * args.steps / max(launches, 1),
                      "avg_launch_ms": step_ms / max(launches, 1)},
         "phases_ms_last_step": {k: round(v, 3) for k, v in tm_last.items()},
+        "tuning": tuning if tuning is not None else ctx.get_tuning(),
     }
+    if not args.no_mixed and not args.mixed:
+        # mixed forms on the same Sigma: complex64 inversion + two or one FP64
+        # refinement steps, and complex64 alone (the low-precision phase of
+        # the switching loop); error vs the FP64 step from that Sigma
+        sig_fixed = ctx.get_sigma()
+        ctx.compute_gloc(fkdmft.FK_FP64)
+        g64 = ctx.get_gloc()
+        j64 = ctx.get_current()[1]
+        mixed = {}
+        for ir in (2, 1, 0):
+            ctx.set_sigma(sig_fixed)
+            ctx.set_refinement(ir)
+            ctx.compute_gloc(fkdmft.FK_MIXED)      # allocation + warmup
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            resid = ctx.compute_gloc(fkdmft.FK_MIXED)
+            tmm = ctx.timings()
+            ctx.impurity_update()
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            g = ctx.get_gloc()
+            j = ctx.get_current()[1]
+            mixed[f"ir{ir}"] = {
+                "sec_per_iter": tb - ta,
+                "gloc_max_rel_err_vs_fp64": float(np.max(np.abs(g - g64)) / np.max(np.abs(g64))),
+                "current_max_rel_err_vs_fp64": float(np.max(np.abs(j - j64)) / np.max(np.abs(j64))),
+                "refine_residual": resid,
+                "phases_ms": {k: round(v, 3) for k, v in tmm.items()},
+                "fp32_inversion_tflops": 8.0 * n ** 3 * npts / (tmm["step_kernels_ms"] * 1e-3) / 1e12,
+            }
+            log(f"bench: mixed ir={ir} done")
+        out["mixed"] = mixed
     if args.converge:
-        ctx2 = fkdmft.Context(stream=stream, **w.kwargs())
-        t2 = time.perf_counter()
-        r = ctx2.iterate(200, tol=configs.C2_TOL, precision=prec)
-        out["converge"] = {"iters": r["iters"], "delta": r["delta"],
-                           "converged": r["converged"],
-                           "seconds": time.perf_counter() - t2}
-        ctx2.close()
+        for name, p2, ir in (("fp64", fkdmft.FK_FP64, 0), ("mixed_switch", fkdmft.FK_MIXED, 0)):
+            ctx2 = fkdmft.Context(stream=stream, **w.kwargs())
+            t_now = ctx.get_tuning()
+            ctx2.set_tuning(tile_rows=t_now["tile_rows"], batch=t_now["batch"],
+                            lookahead=t_now["lookahead"])
+            ctx2.set_refinement(ir)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            r = ctx2.iterate(200, tol=configs.C2_TOL, precision=p2)
+            torch.cuda.synchronize()
+            out.setdefault("converge", {})[name] = {
+                "iters": r["iters"], "delta": r["delta"], "converged": r["converged"],
+                "seconds": time.perf_counter() - t2}
+            log(f"bench: converge {name}: {r['iters']} iterations")
+            ctx2.close()
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -158,8 +158,9 @@ fk_status fk_impurity_update(fk_ctx* ctx, double* max_dsigma_out);
  * update -> Sigma(n); stops after the iteration with delta < tol (converged,
  * FK_OK) or after max_iter iterations (FK_ENOTCONV unless tol <= 0, in which
  * case exactly max_iter iterations run and FK_OK is returned).
- * With FK_MIXED the loop runs complex64+refinement steps while delta >=
- * switch_tol (fk_set_switch, default 1e-5) and FK_FP64 steps afterwards.
+ * With FK_MIXED the loop runs complex64 (+ refinement) steps until delta <
+ * switch_tol (fk_set_switch, default 1e-5) or delta stops contracting
+ * (delta(n) > 0.7 delta(n-1): the complex64 noise floor), FK_FP64 afterwards.
  * delta_history (nullable, max_iter doubles) receives delta(n). */
 fk_status fk_iterate(fk_ctx* ctx, int max_iter, double tol, fk_precision prec,
                      int* iters_out, double* delta_out, double* delta_history);

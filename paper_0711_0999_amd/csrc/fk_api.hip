@@ -755,6 +755,7 @@ extern "C" fk_status fk_iterate(fk_ctx* c, int max_iter, double tol,
   if (!c || max_iter < 1) return FK_EINVAL;
   const size_t mat = sizeof(c64) * (size_t)c->ci.n_c * c->ci.n_c;
   double delta = std::numeric_limits<double>::infinity();
+  double prev_delta = delta;
   bool low = (prec == FK_MIXED);
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
@@ -772,7 +773,11 @@ extern "C" fk_status fk_iterate(fk_ctx* c, int max_iter, double tol,
                              c->st));
     s = impurity(c, nullptr);
     if (s != FK_OK) return s;
-    if (low && delta < c->switch_tol) low = false;
+    // leave the low-precision phase below switch_tol, or as soon as delta
+    // stops contracting (it has reached the complex64 noise floor)
+    if (low && (delta < c->switch_tol || (it > 2 && delta > 0.7 * prev_delta)))
+      low = false;
+    prev_delta = delta;
     if (delta < tol) break;
   }
   if (it > max_iter) it = max_iter;
