@@ -232,6 +232,86 @@ fk_status fk_batch_set_tuning(fk_batch* b, const fk_tuning* t);
 /* out4: last sweep ms, total sweep ms, graph recordings, last recording ms. */
 fk_status fk_batch_timings(const fk_batch* b, double* out4);
 
+/* ---- learned warm start ------------------------------------------------- */
+
+/* A fully connected network of `depth` layers (depth - 1 hidden tanh layers of
+ * `width`, linear output) that predicts, pointwise on contour pairs (t_i, t_j),
+ * the change of Sigma from the previous field to the current one.  Parameters
+ * are float32, packed layer by layer as W_l (out x in, row-major) then b_l.
+ * Training: mean squared error, Adam (b1 0.9, b2 0.999, eps 1e-8) on FP32
+ * matrix cores; inference in FP32 or BF16 (bf16 matrix cores, FP32
+ * accumulation).  Row-major device arrays: x [rows x d_in], y, t [rows x d_out]. */
+typedef struct fk_mlp fk_mlp;
+fk_status fk_mlp_create(int d_in, int width, int depth, int d_out,
+                        const float* params_host, fk_mlp** out);
+fk_status fk_mlp_destroy(fk_mlp* a);                     /* NULL-safe */
+const char* fk_mlp_last_error(const fk_mlp* a);
+fk_status fk_mlp_n_params(const fk_mlp* a, long long* n);
+fk_status fk_mlp_get_params(const fk_mlp* a, float* params_host);
+/* Replaces the parameters and clears the Adam state. */
+fk_status fk_mlp_set_params(fk_mlp* a, const float* params_host);
+fk_status fk_mlp_forward(fk_mlp* a, const float* x_dev, int rows, float* y_dev,
+                         int bf16);
+/* Loss of one batch and its gradient (host array of n_params, nullable). */
+fk_status fk_mlp_loss_grad(fk_mlp* a, const float* x_dev, const float* t_dev,
+                           int rows, double* loss, float* grad_host);
+/* `steps` Adam steps, each on `batch` rows drawn uniformly with replacement
+ * from the `rows` rows of (x, t) by a counter-based hash of (seed, step, slot)
+ * (SplitMix64), gathered on the device; loss_hist[steps] nullable receives the
+ * loss of each minibatch before its step. */
+fk_status fk_mlp_train(fk_mlp* a, const float* x_dev, const float* t_dev,
+                       int rows, int batch, int steps, float lr,
+                       unsigned long long seed, double* loss_hist);
+
+/* Rank-r randomized SVD (basic range finder of Halko, Martinsson & Tropp 2011)
+ * of D Sigma D, D = diag(sqrt|W_j|), for an N_c x N_c complex128 device matrix
+ * Sigma (values Sigma(z_i, z_j) on this context's contour): Y = D Sigma D Omega
+ * with the caller's real N_c x rank host matrix Omega (row-major), Q an
+ * orthonormal basis of range(Y) (modified Gram-Schmidt, twice), and sv_out the
+ * rank singular values (descending) of Q^H D Sigma D.  The weighting makes them
+ * approximate the singular values of the contour integral operator, independent
+ * of the step sizes.  rank <= 256; the small eigen-solve runs on the host. */
+fk_status fk_ws_sketch(fk_ctx* ctx, const double* sigma_dev, int rank,
+                       const double* omega_host, double* sv_out);
+/* Feature rows for pairs p = i*N_c + j (idx_dev: rows int64 pair indices, or
+ * NULL for all N_c^2 pairs in order) of this context's contour and field E
+ * (T = t_max - t_min; t+ = max(t, 0) on the real branches, 0 on the imaginary):
+ *   glob[n_glob] | branch one-hot of i (3), of j (3) | t_i/T, tau_i/beta,
+ *   t_j/T, tau_j/beta | [i >= j] | [i - j >= 2] | (t_i - t_j)/T |
+ *   max(t_i,t_j,0)/T | sin E t_i+, cos E t_i+, sin E t_j+, cos E t_j+ |
+ *   scale*Re, scale*Im of Sigma_prev(i,j) | zero padding to d_in.
+ * d_in >= n_glob + FK_WS_FEATURES, else FK_EINVAL.  A pair index outside
+ * [0, N_c^2) yields a row of NaN (fk_ws_targets: a NaN target). */
+#define FK_WS_FEATURES 20
+fk_status fk_ws_features(fk_ctx* ctx, const double* sigma_prev_dev,
+                         const float* glob_host, int n_glob,
+                         const long long* idx_dev, long long rows, double scale,
+                         float* x_dev, int d_in);
+/* t = scale * (Sigma_new - Sigma_prev) at the pairs (2 floats per row). */
+fk_status fk_ws_targets(fk_ctx* ctx, const double* sigma_prev_dev,
+                        const double* sigma_new_dev, const long long* idx_dev,
+                        long long rows, double scale, float* t_dev);
+/* Sets the context's Sigma to Sigma_prev + y / scale (y: N_c^2 rows of 2;
+ * sigma_prev_dev may be the context's own Sigma buffer). */
+fk_status fk_ws_apply(fk_ctx* ctx, const double* sigma_prev_dev,
+                      const float* y_dev, double scale);
+/* The self-consistency loop of fk_iterate started from the context's current
+ * Sigma (a proposed start, e.g. from fk_ws_apply) and judged by the plain
+ * iteration: the start is kept if its first iteration changes Sigma by at most
+ * `accept` times max|Sigma_start - Sigma_fallback| (a start equal to the
+ * fallback is simply iterated); otherwise, or if a later
+ * FP64 iteration grows delta three times in a row, or a step meets a singular
+ * or non-finite matrix, the loop restarts from fallback_dev (an N_c x N_c
+ * device matrix, e.g. the previous field's Sigma; NULL: Sigma = 0).  iters_out
+ * counts every iteration run, the abandoned ones included (max_iter >= 2);
+ * delta_history as for fk_iterate, with +inf again at a restart.  outcome
+ * (nullable): 0 start kept, 1 rejected after its first iteration, 2 abandoned
+ * later. */
+fk_status fk_iterate_judged(fk_ctx* ctx, const double* fallback_dev,
+                            double accept, int max_iter, double tol,
+                            fk_precision prec, int* iters_out, double* delta_out,
+                            double* delta_history, int* outcome);
+
 #ifdef __cplusplus
 }
 #endif

@@ -749,40 +749,132 @@ extern "C" fk_status fk_impurity_update(fk_ctx* c, double* max_dsigma_out) {
   return impurity(c, max_dsigma_out);
 }
 
+namespace {
+// One self-consistency iteration (the it-th of a run): lattice step, delta =
+// max |G_loc - G_loc of the previous iteration| from the second iteration on,
+// impurity update (dsig: max |Sigma_new - Sigma|, nullable).  In a mixed run the
+// low-precision phase ends below switch_tol, or as soon as delta stops
+// contracting (it has reached the complex64 noise floor).
+fk_status iteration(fk_ctx* c, int it, bool* low, double* delta, double* prev_delta,
+                    double* hist, double* dsig) {
+  fk_status s = fk_compute_gloc(c, *low ? FK_MIXED : FK_FP64, nullptr);
+  if (s != FK_OK) return s;
+  if (it > 1) {
+    HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
+    HIPCHK(c, launch_maxabs(c->d_gloc, c->d_gprev, (size_t)c->ci.n_c * c->ci.n_c,
+                            c->d_key, c->st));
+    *delta = read_key(c, &s);
+    if (s != FK_OK) return s;
+  }
+  if (hist) hist[it - 1] = *delta;
+  HIPCHK(c, hipMemcpyAsync(c->d_gprev, c->d_gloc,
+                           sizeof(c64) * (size_t)c->ci.n_c * c->ci.n_c,
+                           hipMemcpyDeviceToDevice, c->st));
+  s = impurity(c, dsig);
+  if (s != FK_OK) return s;
+  if (*low && (*delta < c->switch_tol || (it > 2 && *delta > 0.7 * *prev_delta)))
+    *low = false;
+  *prev_delta = *delta;
+  return FK_OK;
+}
+}  // namespace
+
 extern "C" fk_status fk_iterate(fk_ctx* c, int max_iter, double tol,
                                 fk_precision prec, int* iters_out,
                                 double* delta_out, double* hist) {
   if (!c || max_iter < 1) return FK_EINVAL;
-  const size_t mat = sizeof(c64) * (size_t)c->ci.n_c * c->ci.n_c;
   double delta = std::numeric_limits<double>::infinity();
   double prev_delta = delta;
   bool low = (prec == FK_MIXED);
   int it = 0;
   for (it = 1; it <= max_iter; ++it) {
-    fk_status s = fk_compute_gloc(c, low ? FK_MIXED : FK_FP64, nullptr);
+    fk_status s = iteration(c, it, &low, &delta, &prev_delta, hist, nullptr);
     if (s != FK_OK) return s;
-    if (it > 1) {
-      HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
-      HIPCHK(c, launch_maxabs(c->d_gloc, c->d_gprev, (size_t)c->ci.n_c * c->ci.n_c,
-                              c->d_key, c->st));
-      delta = read_key(c, &s);
-      if (s != FK_OK) return s;
-    }
-    if (hist) hist[it - 1] = delta;
-    HIPCHK(c, hipMemcpyAsync(c->d_gprev, c->d_gloc, mat, hipMemcpyDeviceToDevice,
-                             c->st));
-    s = impurity(c, nullptr);
-    if (s != FK_OK) return s;
-    // leave the low-precision phase below switch_tol, or as soon as delta
-    // stops contracting (it has reached the complex64 noise floor)
-    if (low && (delta < c->switch_tol || (it > 2 && delta > 0.7 * prev_delta)))
-      low = false;
-    prev_delta = delta;
     if (delta < tol) break;
   }
   if (it > max_iter) it = max_iter;
   if (iters_out) *iters_out = it;
   if (delta_out) *delta_out = delta;
+  if (tol > 0.0 && !(delta < tol))
+    return set_err(c, FK_ENOTCONV, "not converged after %d iterations (delta %.3e)",
+                   max_iter, delta);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_iterate_judged(fk_ctx* c, const double* fallback_dev,
+                                       double accept, int max_iter, double tol,
+                                       fk_precision prec, int* iters_out,
+                                       double* delta_out, double* hist,
+                                       int* outcome) {
+  if (!c || max_iter < 2 || !(accept > 0.0)) return FK_EINVAL;
+  const size_t nn = (size_t)c->ci.n_c * c->ci.n_c;
+  const c64* fb = reinterpret_cast<const c64*>(fallback_dev);
+  fk_status s;
+  // size of the proposed move away from the fallback start
+  HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
+  HIPCHK(c, launch_maxabs(c->d_sigma, fb, nn, c->d_key, c->st));
+  const double move = read_key(c, &s);
+  if (s != FK_OK) return s;
+  double delta = std::numeric_limits<double>::infinity();
+  double prev_delta = delta;
+  bool low = (prec == FK_MIXED);
+  int result = 0;   // 0 accepted, 1 rejected by the first residual, 2 abandoned later
+  int it = 0, base = 0;
+  bool judged = false;
+  int rising = 0;
+  if (!(move <= std::numeric_limits<double>::max())) result = 1;
+  if (move == 0.0) judged = true;   // the start is the fallback itself
+  for (it = 1; result == 0 && it <= max_iter; ++it) {
+    double dsig = 0.0;
+    const double before = delta;
+    const bool was_low = low;
+    s = iteration(c, it, &low, &delta, &prev_delta, hist, judged ? nullptr : &dsig);
+    if (s == FK_ENONFINITE || s == FK_ESINGULAR) {
+      result = judged ? 2 : 1;
+      judged = true;   // the failed iteration is counted
+      break;
+    }
+    if (s != FK_OK) return s;
+    if (!judged) {
+      judged = true;
+      // accept the start if one iteration moves Sigma by at most `accept` times
+      // the distance between the start and the fallback
+      if (!(dsig <= accept * move)) {
+        result = 1;
+        break;
+      }
+    }
+    if (delta < tol) break;
+    // abandon a start whose FP64 iteration grows three times in a row
+    rising = (it > 2 && !was_low && delta > before) ? rising + 1 : 0;
+    if (rising >= 3) {
+      result = 2;
+      break;
+    }
+  }
+  if (result != 0) {
+    // restart from the fallback; the iterations spent so far are counted
+    base = judged ? std::min(it, max_iter) : 0;
+    if (fb)
+      HIPCHK(c, hipMemcpyAsync(c->d_sigma, fb, sizeof(c64) * nn, hipMemcpyDeviceToDevice,
+                               c->st));
+    else
+      HIPCHK(c, fill_f64(reinterpret_cast<double*>(c->d_sigma), 0.0, 2 * nn, c->st));
+    delta = prev_delta = std::numeric_limits<double>::infinity();
+    low = (prec == FK_MIXED);
+    for (it = 1; base + it <= max_iter; ++it) {
+      s = iteration(c, it, &low, &delta, &prev_delta, hist ? hist + base : nullptr,
+                    nullptr);
+      if (s != FK_OK) return s;
+      if (delta < tol) break;
+    }
+    it = std::min(base + it, max_iter);
+  } else if (it > max_iter) {
+    it = max_iter;
+  }
+  if (iters_out) *iters_out = it;
+  if (delta_out) *delta_out = delta;
+  if (outcome) *outcome = result;
   if (tol > 0.0 && !(delta < tol))
     return set_err(c, FK_ENOTCONV, "not converged after %d iterations (delta %.3e)",
                    max_iter, delta);

@@ -83,6 +83,30 @@ SIGNATURES = {
     "fk_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "fk_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "fk_mlp_destroy": (ctypes.c_int, [_vp]),
+    "fk_mlp_last_error": (ctypes.c_char_p, [_vp]),
+    "fk_mlp_n_params": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_longlong)]),
+    "fk_mlp_get_params": (ctypes.c_int, [_vp, _vp]),
+    "fk_mlp_set_params": (ctypes.c_int, [_vp, _vp]),
+    "fk_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int]),
+    "fk_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _dp, _vp]),
+    "fk_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_float, ctypes.c_ulonglong,
+                                    _dp]),
+    "fk_iterate_judged": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_double), _dp,
+                                         ctypes.POINTER(ctypes.c_int)]),
+    "fk_ws_sketch": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _dp]),
+    "fk_ws_features": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp,
+                                      ctypes.c_longlong, ctypes.c_double, _vp,
+                                      ctypes.c_int]),
+    "fk_ws_targets": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_longlong,
+                                     ctypes.c_double, _vp]),
+    "fk_ws_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double]),
     "fk_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Contour),
                                        ctypes.POINTER(Model), ctypes.POINTER(_vp)]),
     "fk_batch_destroy": (ctypes.c_int, [_vp]),
@@ -299,6 +323,51 @@ class Context:
         self._check(self._lib.fk_get_tuning(self._h, ctypes.byref(t)), "fk_get_tuning")
         return t.as_dict()
 
+    def iterate_judged(self, fallback, max_iter, tol=0.0, accept=0.5,
+                       precision=FK_FP64):
+        """fk_iterate_judged from the current Sigma; fallback: torch device
+        matrix or None (Sigma = 0)."""
+        it = ctypes.c_int()
+        d = ctypes.c_double()
+        oc = ctypes.c_int()
+        hist = np.zeros(max_iter)
+        fp = None if fallback is None else self._matrix_arg(fallback, False)
+        if fp is not None and fp[1] != 1:
+            raise ValueError("fallback must be a device tensor")
+        s = self._lib.fk_iterate_judged(self._h, None if fp is None else fp[0],
+                                        float(accept), max_iter, tol, precision,
+                                        ctypes.byref(it), ctypes.byref(d), _dptr(hist),
+                                        ctypes.byref(oc))
+        if s not in (FK_OK, FK_ENOTCONV):
+            self._check(s, "fk_iterate_judged")
+        return dict(iters=it.value, delta=d.value, history=hist[:it.value],
+                    converged=(s == FK_OK and tol > 0), outcome=oc.value)
+
+    # -- learned warm start (device tensors: torch, contiguous)
+    def ws_sketch(self, sigma_dev, omega):
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        sv = np.zeros(om.shape[1])
+        self._check(self._lib.fk_ws_sketch(self._h, sigma_dev.data_ptr(), om.shape[1],
+                                           om.ctypes.data, _dptr(sv)), "fk_ws_sketch")
+        return sv
+
+    def ws_features(self, sigma_prev_dev, glob, idx_dev, rows, scale, x_dev, d_in):
+        g = np.ascontiguousarray(glob, dtype=np.float32)
+        self._check(self._lib.fk_ws_features(
+            self._h, sigma_prev_dev.data_ptr(), g.ctypes.data, len(g),
+            None if idx_dev is None else idx_dev.data_ptr(), rows, float(scale),
+            x_dev.data_ptr(), d_in), "fk_ws_features")
+
+    def ws_targets(self, sigma_prev_dev, sigma_new_dev, idx_dev, rows, scale, t_dev):
+        self._check(self._lib.fk_ws_targets(
+            self._h, sigma_prev_dev.data_ptr(), sigma_new_dev.data_ptr(),
+            None if idx_dev is None else idx_dev.data_ptr(), rows, float(scale),
+            t_dev.data_ptr()), "fk_ws_targets")
+
+    def ws_apply(self, sigma_prev_dev, y_dev, scale):
+        self._check(self._lib.fk_ws_apply(self._h, sigma_prev_dev.data_ptr(),
+                                          y_dev.data_ptr(), float(scale)), "fk_ws_apply")
+
     def timings(self):
         out = np.zeros(7)
         self._check(self._lib.fk_timings(self._h, _dptr(out)), "fk_timings")
@@ -400,3 +469,79 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class MLP:
+    """fk_mlp: depth linear layers (tanh between), float32 parameters packed as
+    W_l (out x in) then b_l.  Tensors passed in are torch float32 on the GPU."""
+
+    def __init__(self, d_in, width, depth, d_out, params=None, seed=0):
+        lib = library()
+        self._lib = lib
+        self.d_in, self.width, self.depth, self.d_out = d_in, width, depth, d_out
+        dims = [d_in] + [width] * (depth - 1) + [d_out]
+        self.shapes = [(dims[i + 1], dims[i]) for i in range(depth)]
+        if params is None:
+            rng = np.random.default_rng(seed)
+            parts = []
+            for o, i in self.shapes:
+                parts.append((rng.standard_normal((o, i)) * np.sqrt(1.0 / i)).ravel())
+                parts.append(np.zeros(o))
+            params = np.concatenate(parts)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        h = _vp()
+        st = lib.fk_mlp_create(d_in, width, depth, d_out, p.ctypes.data, ctypes.byref(h))
+        if st != FK_OK:
+            raise FkError(st, "fk_mlp_create")
+        self._h = h
+        n = ctypes.c_longlong()
+        lib.fk_mlp_n_params(h, ctypes.byref(n))
+        self.n_params = n.value
+
+    def _check(self, s, what):
+        if s != FK_OK:
+            raise FkError(s, f"{what}: {self._lib.fk_mlp_last_error(self._h).decode()}")
+
+    def get_params(self):
+        p = np.zeros(self.n_params, np.float32)
+        self._check(self._lib.fk_mlp_get_params(self._h, p.ctypes.data), "get_params")
+        return p
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        self._check(self._lib.fk_mlp_set_params(self._h, p.ctypes.data), "set_params")
+
+    def forward(self, x, bf16=False):
+        import torch
+        assert x.is_contiguous() and x.dtype == torch.float32 and x.shape[1] == self.d_in
+        y = torch.empty((x.shape[0], self.d_out), dtype=torch.float32, device=x.device)
+        self._check(self._lib.fk_mlp_forward(self._h, x.data_ptr(), x.shape[0],
+                                             y.data_ptr(), int(bf16)), "fk_mlp_forward")
+        return y
+
+    def loss_grad(self, x, t):
+        loss = ctypes.c_double()
+        g = np.zeros(self.n_params, np.float32)
+        self._check(self._lib.fk_mlp_loss_grad(self._h, x.data_ptr(), t.data_ptr(),
+                                               x.shape[0], ctypes.byref(loss),
+                                               g.ctypes.data), "fk_mlp_loss_grad")
+        return loss.value, g
+
+    def train(self, x, t, batch, steps, lr, seed=0):
+        hist = np.zeros(steps)
+        self._check(self._lib.fk_mlp_train(self._h, x.data_ptr(), t.data_ptr(),
+                                           x.shape[0], batch, steps, float(lr),
+                                           int(seed), _dptr(hist)), "fk_mlp_train")
+        return hist
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fk_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

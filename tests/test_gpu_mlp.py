@@ -1,0 +1,193 @@
+"""The warm-start network's kernels (forward FP32 and BF16, backward, Adam with
+library-drawn minibatches), the warm-start I/O (randomized sketch, feature rows,
+targets, proposal) and the judged loop, through the C ABI, against the oracle.
+
+Bars: FP32 network arithmetic vs the float64 oracle, max-abs error / max-abs
+value <= 1e-4 (loss, gradient, outputs); BF16 outputs vs the oracle with
+operands rounded to bfloat16, <= 3e-3 (activations are rounded from float32 on
+the device, from float64 in the oracle); sketch and proposal in FP64, 1e-10;
+feature rows (float32 of float64 values) 1e-6 absolute.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle import warmstart as ows
+from paper_0711_0999_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+SMALL = dict(t_min=-1.0, t_max=2.0, dt=0.1, dtau=0.1, beta=1.3, U=1.0, E=1.5,
+             n_eps=3, n_ebar=4)             # N_c = 73
+
+
+def test_gradient_matches_oracle(lib):
+    """Width 96 and 200 rows: ragged against the 64 x 64 tiles in every GEMM."""
+    say("case: network loss and gradient, d_in 64, width 96, depth 4, rows 200")
+    shapes = omlp.layer_shapes(64, 96, 4, 2)
+    p = inputs.network_params(shapes, seed=1)
+    x = inputs.random_rows(200, 64, seed=2)
+    t = inputs.random_rows(200, 2, seed=3)
+    net = lib.MLP(64, 96, 4, 2, params=p)
+    assert net.n_params == omlp.n_params(shapes)
+    loss, g = net.loss_grad(dev(x), dev(t))
+    lo, go = omlp.loss_and_grad(p.astype(np.float64), shapes, x.astype(np.float64),
+                                t.astype(np.float64))
+    assert abs(loss - lo) < 1e-5 * lo
+    assert relerr(g, go) < 1e-4
+    for (o, i), (gw, gb), (gwo, gbo) in zip(shapes, omlp.unpack(g, shapes),
+                                            omlp.unpack(go, shapes)):
+        assert relerr(gw, gwo) < 1e-4 and relerr(gb, gbo) < 1e-4, (o, i)
+    net.close()
+
+
+@pytest.mark.parametrize("rows", [1, 1000])
+def test_forward_fp32_and_bf16(lib, rows):
+    say(f"case: network forward, width 512, depth 4, rows {rows}")
+    shapes = omlp.layer_shapes(64, 512, 4, 2)
+    p = inputs.network_params(shapes, seed=4)
+    x = inputs.random_rows(rows, 64, seed=5)
+    net = lib.MLP(64, 512, 4, 2, params=p)
+    xd = dev(x)
+    y32 = net.forward(xd, bf16=False).cpu().numpy()
+    y16 = net.forward(xd, bf16=True).cpu().numpy()
+    yo, _ = omlp.forward(p.astype(np.float64), shapes, x.astype(np.float64))
+    yob, _ = omlp.forward(p.astype(np.float64), shapes, x.astype(np.float64), bf16=True)
+    assert relerr(y32, yo) < 1e-4
+    assert relerr(y16, yob) < 3e-3
+    if rows > 1:
+        assert relerr(y16, yo) > 1e-4          # the bf16 path really rounds
+    net.close()
+
+
+def test_adam_steps_match_oracle(lib):
+    """Five Adam steps on minibatches of 16 of 50 rows, drawn by the library's
+    SplitMix64 sampler and by the oracle's own implementation of it."""
+    say("case: five Adam steps vs oracle")
+    shapes = omlp.layer_shapes(64, 80, 4, 2)
+    p = inputs.network_params(shapes, seed=6)
+    x = inputs.random_rows(50, 64, seed=7)
+    t = inputs.random_rows(50, 2, seed=8)
+    net = lib.MLP(64, 80, 4, 2, params=p)
+    hist = net.train(dev(x), dev(t), batch=16, steps=5, lr=1e-3, seed=11)
+    po, lo = omlp.train(p.astype(np.float64), shapes, x.astype(np.float64),
+                        t.astype(np.float64), 16, 5, 1e-3, seed=11)
+    assert relerr(hist, lo) < 1e-4
+    d = np.abs(net.get_params() - po)
+    # parameters with a tiny gradient can take a different Adam step in FP32
+    assert np.quantile(d, 0.999) < 1e-5 and d.max() < 1e-2
+    net.close()
+
+
+def test_training_fits_a_smooth_map(lib):
+    say("case: training reduces the loss")
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-1, 1, (20000, 64)).astype(np.float32)
+    t = np.stack([np.sin(3 * x[:, 0]) * x[:, 1], np.cos(2 * x[:, 2] + x[:, 3])],
+                 axis=1).astype(np.float32)
+    net = lib.MLP(64, 256, 4, 2, seed=1)
+    h = net.train(dev(x), dev(t), batch=1024, steps=600, lr=1e-3, seed=3)
+    assert np.mean(h[-50:]) < 0.1 * np.mean(h[:10])
+    net.close()
+
+
+def test_sketch_matches_oracle(lib):
+    say("case: randomized sketch, N_c 73, rank 8")
+    with lib.Context(**SMALL) as c:
+        z, w = c.contour_points()
+        om = np.random.default_rng(3).standard_normal((c.n_c, 8))
+        sig = inputs.random_sigma(c.n_c, seed=13)
+        sv = c.ws_sketch(dev(sig), om)
+        assert relerr(sv, ows.weighted_sketch(sig, w, om)) < 1e-10
+        ones = np.ones((c.n_c, c.n_c), complex)
+        sv1 = c.ws_sketch(dev(ones), om)
+        assert abs(sv1[0] - (2 * 3.0 + 1.3)) < 1e-11 and np.all(sv1[1:] < 1e-10)
+        assert np.all(c.ws_sketch(dev(np.zeros_like(ones)), om) == 0.0)
+
+
+@pytest.mark.parametrize("use_idx", [True, False])
+def test_features_targets_and_apply(lib, use_idx):
+    say(f"case: feature rows, targets, proposal (idx {use_idx})")
+    with lib.Context(**SMALL) as c:
+        n = c.n_c
+        z, w = c.contour_points()
+        sp = inputs.random_sigma(n, seed=14)
+        sn = inputs.random_sigma(n, seed=15)
+        glob = inputs.random_rows(1, 5, seed=16)[0]
+        idx = inputs.pair_indices(n, 1001, seed=17) if use_idx else None
+        rows = 1001 if use_idx else n * n
+        x = torch.empty((rows, 32), dtype=torch.float32, device="cuda")
+        t = torch.empty((rows, 2), dtype=torch.float32, device="cuda")
+        di = dev(idx) if use_idx else None
+        c.ws_features(dev(sp), glob, di, rows, 0.7, x, 32)
+        c.ws_targets(dev(sp), dev(sn), di, rows, 0.7, t)
+        xo = ows.features(z, c.n_t, 3.0, 1.3, 1.5, sp, glob.astype(np.float64), idx, 0.7, 32)
+        assert np.max(np.abs(x.cpu().numpy() - xo)) < 1e-6
+        assert relerr(t.cpu().numpy(), ows.targets(sp, sn, idx, 0.7)) < 1e-6
+        y = inputs.random_rows(n * n, 2, seed=18)
+        c.ws_apply(dev(sp), dev(y), 0.7)
+        assert relerr(c.get_sigma(), ows.apply(sp, y.astype(np.float64), 0.7)) < 1e-12
+        with pytest.raises(lib.FkError):
+            c.ws_features(dev(sp), glob, di, rows, 0.7, x, 24)   # d_in too small
+
+
+def test_judged_loop_accepts_rejects_and_falls_back(lib):
+    say("case: judged loop")
+    kw = dict(SMALL, U=1.5)
+    tol = 1e-10
+    with lib.Context(**kw) as c:
+        r = c.iterate(200, tol=tol)
+        fixed = torch.empty((c.n_c, c.n_c), dtype=torch.complex128, device="cuda")
+        c.get_sigma(fixed)
+        g_fixed = c.get_gloc()
+    with lib.Context(**dict(kw, E=1.25)) as c:
+        c.iterate(200, tol=tol)
+        prev = torch.empty_like(fixed)
+        c.get_sigma(prev)
+    with lib.Context(**kw) as c:            # plain loop from the previous field
+        c.set_sigma(prev)
+        plain = c.iterate(200, tol=tol)
+        g_plain = c.get_gloc()
+    # the fixed point itself is accepted and converges at once
+    with lib.Context(**kw) as c:
+        c.set_sigma(fixed)
+        r = c.iterate_judged(prev, 200, tol=tol)
+        assert r["outcome"] == 0 and r["iters"] == 2 and r["converged"]
+        assert np.max(np.abs(c.get_gloc() - g_fixed)) < 1e-9
+    # a far-off start is rejected after one iteration; the restart from the
+    # fallback is the plain loop, bit for bit
+    bad = (prev.cpu().numpy() + 5.0 * inputs.random_sigma(prev.shape[0], seed=19))
+    with lib.Context(**kw) as c:
+        c.set_sigma(bad)
+        r = c.iterate_judged(prev, 200, tol=tol)
+        assert r["outcome"] == 1 and r["iters"] == plain["iters"] + 1
+        assert np.isinf(r["history"][1])
+        assert np.array_equal(c.get_gloc(), g_plain)
+    # a non-finite start falls back before any iteration
+    nan = prev.cpu().numpy().copy()
+    nan[2, 3] = np.nan
+    with lib.Context(**kw) as c:
+        c.set_sigma(nan)
+        r = c.iterate_judged(prev, 200, tol=tol)
+        assert r["outcome"] == 1 and r["iters"] == plain["iters"]
+        assert np.array_equal(c.get_gloc(), g_plain)
+    # the fallback itself as the start: simply iterated
+    with lib.Context(**kw) as c:
+        c.set_sigma(prev)
+        r = c.iterate_judged(prev, 200, tol=tol)
+        assert r["outcome"] == 0 and r["iters"] == plain["iters"]

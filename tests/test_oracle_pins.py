@@ -438,3 +438,166 @@ def test_impurity_second_order_perturbation():
         pred = u * (w1 - 0.5) * s + u * u * w1 * (1 - w1) * (s @ g0eff_r @ s)
         rem.append(np.max(np.abs(got - pred)))
     assert rem[0] / rem[1] > 6.0, rem
+
+
+# ----------------------------------------------------------- warm-start net
+def test_mlp_backprop_matches_finite_differences():
+    """The numpy reference gradient of the warm-start network equals central
+    finite differences of its loss (pins the backward pass)."""
+    from oracle import mlp
+    rng = np.random.default_rng(4)
+    shapes = mlp.layer_shapes(7, 9, 4, 2)
+    p = 0.4 * rng.standard_normal(mlp.n_params(shapes))
+    x = rng.standard_normal((5, 7))
+    t = rng.standard_normal((5, 2))
+    loss, g = mlp.loss_and_grad(p, shapes, x, t)
+    h = 1e-6
+    idx = rng.choice(len(p), 40, replace=False)
+    for k in idx:
+        e = np.zeros_like(p)
+        e[k] = h
+        fd = (mlp.loss_and_grad(p + e, shapes, x, t)[0] -
+              mlp.loss_and_grad(p - e, shapes, x, t)[0]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_randomized_svd_recovers_low_rank_spectrum():
+    """Probing with the top right singular vectors of a matrix, the randomized
+    SVD returns exactly its leading singular values (library SVD); with random
+    probes of a rank-r matrix it returns all r of them, the rest zero."""
+    from oracle import warmstart
+    rng = np.random.default_rng(6)
+    n, r = 40, 6
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    u, sv_full, vh = np.linalg.svd(a)
+    sv = warmstart.randomized_singular_values(a, vh.conj().T[:, :r])
+    assert np.max(np.abs(sv - sv_full[:r])) < 1e-10 * sv_full[0]
+    lo = (rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))) @ \
+        (rng.standard_normal((r, n)) + 1j * rng.standard_normal((r, n)))
+    s2 = warmstart.randomized_singular_values(lo, rng.standard_normal((n, r + 3)))
+    s_lib = np.linalg.svd(lo, compute_uv=False)
+    assert np.max(np.abs(s2[:r] - s_lib[:r])) < 1e-10 * s_lib[0]
+    assert np.all(s2[r:] < 1e-10 * s2[0])
+
+
+def test_bf16_rounding_is_nearest_even():
+    """bfloat16 keeps 7 explicit significand bits: values near 1 are 1 + k/128.
+    Halfway cases go to the even k; anything above halfway rounds up."""
+    from oracle import mlp
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -20,
+                  -(1 + 2.0 ** -8), 3.0, 2.0 ** -130], dtype=np.float32)
+    want = [1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -1.0, 3.0, 2.0 ** -130]
+    assert list(mlp.round_bf16(x)) == want
+
+
+def test_bf16_forward_is_exact_on_bf16_values():
+    """With weights and inputs that bfloat16 represents exactly (small dyadic
+    values) and a linear network of one layer, the bf16 product equals the
+    exact one; on generic values it differs by about 2^-8 relative."""
+    from oracle import mlp
+    rng = np.random.default_rng(9)
+    shapes = mlp.layer_shapes(16, 8, 2, 3)
+    p = rng.integers(-8, 9, mlp.n_params(shapes)) / 16.0
+    x = rng.integers(-8, 9, (4, 16)) / 8.0
+    w, b = mlp.unpack(p, shapes)[0]
+    y0 = x @ w.T + b
+    y, _ = mlp.forward(p, shapes[:1], x, bf16=True)
+    assert np.array_equal(y, y0)
+    pg = rng.standard_normal(mlp.n_params(shapes))
+    xg = rng.standard_normal((64, 16))
+    ya, _ = mlp.forward(pg, shapes, xg)
+    yb, _ = mlp.forward(pg, shapes, xg, bf16=True)
+    rel = np.max(np.abs(ya - yb)) / np.max(np.abs(ya))
+    assert 1e-4 < rel < 3e-2
+
+
+def test_weighted_sketch_of_constant_kernel_is_contour_length():
+    """Sigma = 1 on every pair is rank one: D 1 D = d d^T with d_j = sqrt|W_j|, so
+    its one singular value is sum_j |W_j| = 2 (t_max - t_min) + beta for the
+    rectangle weights of the contour (Sec. II), at every step size."""
+    from oracle import warmstart
+    rng = np.random.default_rng(12)
+    for dt, dtau in [(0.5, 0.25), (0.1, 0.05), (0.025, 0.1)]:
+        z, w = contour.points(-2.0, 3.0, dt, dtau, 1.5)
+        n = len(z)
+        sv = warmstart.weighted_sketch(np.ones((n, n), complex), w,
+                                       rng.standard_normal((n, 4)))
+        assert abs(sv[0] - (2 * 5.0 + 1.5)) < 1e-11
+        assert np.all(sv[1:] < 1e-10)
+
+
+def test_weighted_sketch_converges_with_step_size():
+    """For the separable kernel Sigma(z, z') = f(z) conj(f(z')) with f = cos(Re z)
+    + i Im z the single singular value is the squared L2 norm of f along the
+    contour; the rectangle sums approach it at first order in the step."""
+    from oracle import warmstart
+    t0, t1, beta = -1.0, 2.0, 1.0
+    # exact: two real branches of int cos^2 t dt, imaginary branch
+    # int_0^beta (cos^2 t0 + tau^2) dtau
+    real = (t1 - t0) / 2 + (np.sin(2 * t1) - np.sin(2 * t0)) / 4
+    exact = 2 * real + beta * np.cos(t0) ** 2 + beta ** 3 / 3
+    errs = []
+    for dt in [0.1, 0.05, 0.025]:
+        z, w = contour.points(t0, t1, dt, dt, beta)
+        f = np.cos(z.real) + 1j * z.imag
+        sv = warmstart.weighted_sketch(np.outer(f, f.conj()), w,
+                                       np.random.default_rng(1).standard_normal((len(z), 3)))
+        errs.append(abs(sv[0] - exact))
+    assert errs[0] < 0.2
+    assert 1.6 < errs[0] / errs[1] < 2.4 and 1.6 < errs[1] / errs[2] < 2.4
+
+
+def test_warm_start_feature_rows_by_hand():
+    """Feature rows worked by hand on the contour t in [-1, 1], dt = 0.5,
+    beta = 1, dtau = 0.5 (points: upper -1, -0.5, 0, 0.5; lower 1, 0.5, 0,
+    -0.5; imaginary -1, -1 - 0.5i), E = 2, T = 2."""
+    from oracle import warmstart
+    z, w = contour.points(-1.0, 1.0, 0.5, 0.5, 1.0)
+    n_t = contour.sizes(-1.0, 1.0, 0.5, 0.5, 1.0)[0]
+    assert len(z) == 10 and n_t == 4
+    sp = np.zeros((10, 10), complex)
+    sp[5, 2] = 0.3 - 0.1j
+    sp[1, 3] = -0.25j
+    rows = warmstart.features(z, n_t, 2.0, 1.0, 2.0, sp, [0.7], [52, 99, 13], 2.0, 24)
+    s1, c1 = np.sin(1.0), np.cos(1.0)
+    want = np.zeros((3, 24))
+    want[0, :21] = [0.7, 0, 1, 0, 1, 0, 0, 0.25, 0, 0, 0, 1, 1, 0.25, 0.25,
+                    s1, c1, 0, 1, 0.6, -0.2]
+    want[1, :21] = [0.7, 0, 0, 1, 0, 0, 1, 0, 0.5, 0, 0.5, 1, 0, 0, 0,
+                    0, 1, 0, 1, 0, 0]
+    want[2, :21] = [0.7, 1, 0, 0, 1, 0, 0, -0.25, 0, 0.25, 0, 0, 0, -0.5, 0.25,
+                    0, 1, s1, c1, 0, -0.5]
+    assert np.max(np.abs(rows - want)) < 1e-15
+
+
+def test_splitmix64_published_sequence():
+    """SplitMix64 from state 1234567 gives the sequence of the published
+    reference generator (Vigna's splitmix64.c), the state advancing by the
+    golden-ratio increment."""
+    from oracle import mlp
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    z = 1234567
+    got = []
+    for _ in range(5):
+        got.append(mlp.splitmix64(z))
+        z = (z + 0x9E3779B97F4A7C15) % 2 ** 64
+    assert got == want
+    r = mlp.minibatch_rows(3, 2, 1000, 7)
+    assert r.min() == 0 and r.max() == 6 and abs(np.bincount(r).mean() - 1000 / 7) < 1e-9
+
+
+def test_adam_first_step_moves_every_parameter_by_lr():
+    """Adam's bias correction makes the first step -lr * g / (|g| + eps): every
+    parameter with |g| >> eps moves by lr against its gradient."""
+    from oracle import mlp
+    rng = np.random.default_rng(2)
+    shapes = mlp.layer_shapes(5, 6, 3, 2)
+    p = rng.standard_normal(mlp.n_params(shapes))
+    x = rng.standard_normal((9, 5))
+    t = rng.standard_normal((9, 2))
+    p1, losses = mlp.train(p, shapes, x, t, 9, 1, 1e-3, seed=0)
+    r = mlp.minibatch_rows(0, 0, 9, 9)
+    _, g = mlp.loss_and_grad(p, shapes, x[r], t[r])
+    big = np.abs(g) > 1e-4
+    assert np.allclose((p - p1)[big], 1e-3 * np.sign(g[big]), rtol=1e-3, atol=0)
