@@ -257,7 +257,9 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
     HIPCHK(c, launch_build<T>(c->d_sigt, c->tab, k0, nmat, b.x, b.stride, b.ld,
                               n, c->st));
     HIPCHK(c, hipEventRecord(c->ev[1], c->st));
-    HIPCHK(c, batch_invert<T>(b, nmat, c->st, c->aux, &launches, &c->ev[6]));
+    Aux ax = c->aux;
+    ax.clk = c->clk.on ? &c->clk : nullptr;
+    HIPCHK(c, batch_invert<T>(b, nmat, c->st, ax, &launches, &c->ev[6]));
     HIPCHK(c, hipEventRecord(c->ev[2], c->st));
     HIPCHK(c, launch_reduce<T>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                c->d_rho + k0, nmat, n, c->d_gloc, k0 > 0 ? 1 : 0,
@@ -267,6 +269,7 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
     HIPCHK(c, hipEventRecord(c->ev[3], c->st));
     s = check_status(c, b.status, nmat, k0, "lattice inversion");
     if (s != FK_OK) return s;
+    if (c->clk.on) clock_collect(c->clk);
     c->times[0] += elapsed(c->ev[0], c->ev[1]);
     c->times[1] += elapsed(c->ev[1], c->ev[2]);
     c->times[3] += elapsed(c->ev[2], c->ev[3]);
@@ -473,6 +476,8 @@ void free_ctx(fk_ctx* c) {
   batch_free(c->b32);
   batch_free(c->imp);
   for (hipEvent_t& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->clk.ev)
     if (e) (void)hipEventDestroy(e);
   if (c->aux.evN) (void)hipEventDestroy(c->aux.evN);
   if (c->aux.evP) (void)hipEventDestroy(c->aux.evP);
@@ -878,6 +883,29 @@ extern "C" fk_status fk_iterate_judged(fk_ctx* c, const double* fallback_dev,
   if (tol > 0.0 && !(delta < tol))
     return set_err(c, FK_ENOTCONV, "not converged after %d iterations (delta %.3e)",
                    max_iter, delta);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_set_kernel_clock(fk_ctx* c, int on) {
+  if (!c) return FK_EINVAL;
+  KernelClock& k = c->clk;
+  if (on && k.ev.empty()) {
+    k.ev.assign(2 * (kMaxN / kNBO + 2), nullptr);
+    for (hipEvent_t& e : k.ev) HIPCHK(c, hipEventCreate(&e));
+  }
+  k.on = on != 0;
+  k.used = 0;
+  k.flops.clear();
+  k.ms = k.flop = 0.0;
+  k.launches = 0;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_kernel_clock(const fk_ctx* c, double* out3) {
+  if (!c || !out3) return FK_EINVAL;
+  out3[0] = c->clk.ms;
+  out3[1] = (double)c->clk.launches;
+  out3[2] = c->clk.flop;
   return FK_OK;
 }
 

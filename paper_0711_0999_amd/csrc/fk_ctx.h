@@ -52,6 +52,7 @@ struct fk_ctx {
   fk::Batch<float> b32;            // lattice batch (complex64), lazily
   fk::Batch<double> imp;           // impurity inversions (2 slots)
   fk::Aux aux;                     // look-ahead stream and events
+  fk::KernelClock clk;             // optional timing of the trailing update
   // FP64 refinement buffers of the mixed path (ir_cap matrices)
   int ir_cap = 0;
   fk::c64* ir_x = nullptr;

@@ -231,11 +231,38 @@ hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
                    hipMemcpyHostToDevice);
 }
 
+// Optional timing of the dominant kernel, the trailing update of each outer
+// block ("big" launch): an event pair around every such launch of a uniform
+// batch, with the launch's algorithmic flops, 8 n * cols * K per matrix (n
+// rows, cols outside the two blocks being factored, K the block width).
+struct KernelClock {
+  bool on = false;
+  std::vector<hipEvent_t> ev;   // event pairs
+  std::vector<double> flops;    // per recorded pair
+  int used = 0;                 // events in use
+  double ms = 0.0, flop = 0.0;
+  long long launches = 0;
+};
+
+inline void clock_collect(KernelClock& k) {
+  for (int i = 0; i + 1 < k.used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, k.ev[i], k.ev[i + 1]) == hipSuccess) {
+      k.ms += ms;
+      k.flop += k.flops[i / 2];
+      k.launches++;
+    }
+  }
+  k.used = 0;
+  k.flops.clear();
+}
+
 // Side stream and events of the look-ahead (default priority).
 struct Aux {
   hipStream_t st2 = nullptr;
   hipEvent_t evN = nullptr, evP = nullptr;
   bool lookahead = false;  // factor the next block on st2 (else in order on st)
+  KernelClock* clk = nullptr;
 };
 
 // Invert matrices 0..nmat-1 of the batch in place (permuted storage).  The
@@ -281,10 +308,20 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
       if (ax.lookahead && (e = hipEventRecord(ax.evP, ax.st2)) != hipSuccess) return e;
     }
     const int nB = b.uniform ? nmat * b.cntB[S] : b.totB[S];
+    KernelClock* ck = (ax.clk && b.uniform && nB > 0 &&
+                       ax.clk->used + 2 <= (int)ax.clk->ev.size()) ? ax.clk : nullptr;
+    if (ck && (e = hipEventRecord(ck->ev[ck->used], st)) != hipSuccess) return e;
     if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offB[S],
                            nB, S, b.variant, st)) != hipSuccess)
       return e;
     ++nl;
+    if (ck) {
+      if ((e = hipEventRecord(ck->ev[ck->used + 1], st)) != hipSuccess) return e;
+      const double n = b.n, K = std::min(kNBO, b.n - S * kNBO);
+      const double k1 = next ? std::min(kNBO, b.n - (S + 1) * kNBO) : 0;
+      ck->flops.push_back(8.0 * n * (n - K - k1) * K * nmat);
+      ck->used += 2;
+    }
     if (next && ax.lookahead && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess)
       return e;
   }

@@ -83,6 +83,8 @@ SIGNATURES = {
     "fk_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "fk_set_kernel_clock": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "fk_kernel_clock": (ctypes.c_int, [_vp, _dp]),
     "fk_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "fk_mlp_destroy": (ctypes.c_int, [_vp]),
@@ -322,6 +324,14 @@ class Context:
         t = Tuning()
         self._check(self._lib.fk_get_tuning(self._h, ctypes.byref(t)), "fk_get_tuning")
         return t.as_dict()
+
+    def set_kernel_clock(self, on=True):
+        self._check(self._lib.fk_set_kernel_clock(self._h, int(on)), "fk_set_kernel_clock")
+
+    def kernel_clock(self):
+        out = np.zeros(3)
+        self._check(self._lib.fk_kernel_clock(self._h, _dptr(out)), "fk_kernel_clock")
+        return dict(ms=out[0], launches=int(out[1]), flop=out[2])
 
     def iterate_judged(self, fallback, max_iter, tol=0.0, accept=0.5,
                        precision=FK_FP64):

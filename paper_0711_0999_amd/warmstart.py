@@ -39,6 +39,11 @@ def sigma_scale(u):
     return 1.0 / (0.25 * u * u + 0.01)
 
 
+# The previous Sigma enters the feature rows as PREV_GAIN * sigma_scale(U) *
+# Sigma_prev: sigma_scale brings it to O(0.1-1) across U, the gain to O(1).
+PREV_GAIN = 4.0
+
+
 def contour_length(cont):
     return 2.0 * (cont["t_max"] - cont["t_min"]) + cont["beta"]
 
@@ -86,7 +91,7 @@ class WarmStart:
         n = ctx.n_c
         g = glob_features(ctx, cont, sigma_prev, u, e)
         x = torch.empty((n * n, D_IN), dtype=torch.float32, device="cuda")
-        ctx.ws_features(sigma_prev, g, None, n * n, sigma_scale(u), x, D_IN)
+        ctx.ws_features(sigma_prev, g, None, n * n, PREV_GAIN * sigma_scale(u), x, D_IN)
         y = self.net.forward(x, bf16=bf16)
         ctx.ws_apply(sigma_prev, y, sigma_scale(u) / self.t_rms)
         torch.cuda.synchronize()
@@ -136,7 +141,8 @@ def field_sweep_data(cont, us, es, n_eps, n_ebar, tol, rows_per_run, seed=0,
                         rng.integers(0, n * n, rows_per_run).astype(np.int64)).cuda()
                     xs = x[row:row + rows_per_run]
                     ts = t[row:row + rows_per_run]
-                    c.ws_features(prev[i], g, idx, rows_per_run, sigma_scale(u), xs, D_IN)
+                    c.ws_features(prev[i], g, idx, rows_per_run, PREV_GAIN * sigma_scale(u),
+                                  xs, D_IN)
                     c.ws_targets(prev[i], new[i], idx, rows_per_run, sigma_scale(u), ts)
                     row += rows_per_run
         dt_s = time.perf_counter() - t0
@@ -150,7 +156,7 @@ def field_sweep_data(cont, us, es, n_eps, n_ebar, tol, rows_per_run, seed=0,
     return x[:row], t[:row], stats
 
 
-def train(x, t, steps=(3000, 2000, 1000), lrs=(1e-3, 3e-4, 1e-4), batch=4096,
+def train(x, t, steps=(15000, 10000, 5000), lrs=(3e-4, 1e-4, 3e-5), batch=8192,
           seed=0, log=None):
     """Adam on the sampled pairs (minibatches drawn by the library); the targets
     are divided by their RMS first (host arithmetic on a copy)."""
@@ -161,50 +167,181 @@ def train(x, t, steps=(3000, 2000, 1000), lrs=(1e-3, 3e-4, 1e-4), batch=4096,
     ws = WarmStart(t_rms=t_rms, seed=seed)
     hist = []
     for k, (n, lr) in enumerate(zip(steps, lrs)):
-        h = ws.net.train(x, tn, batch, n, lr, seed=seed * 1000 + k)
-        hist.append(h)
-        if log:
-            log(f"train phase {k}: lr {lr:g}, loss {h[0]:.4f} -> {np.mean(h[-50:]):.4f}")
+        for c0 in range(0, n, 2500):      # chunks, so progress is visible
+            h = ws.net.train(x, tn, batch, min(2500, n - c0), lr,
+                             seed=seed * 1000 + k * 100 + c0 // 2500)
+            hist.append(h)
+            if log:
+                log(f"train phase {k} (lr {lr:g}) steps {c0}..{c0 + len(h)}: "
+                    f"loss {np.mean(h[:50]):.4f} -> {np.mean(h[-50:]):.4f}")
     return ws, np.concatenate(hist)
 
 
+def _error_regions(ctx, cont, prev, start, fixed):
+    """Max error of the previous-field and network starts by region of the
+    pair plane: branch pair, and within the real branches whether the pair is
+    within two indices of the diagonal, before the field (max(t_i, t_j) <= 0)
+    or at the turning point (both within 1 of t_max)."""
+    n, nt = ctx.n_c, ctx.n_t
+    br = np.array([0] * nt + [1] * nt + [2] * (n - 2 * nt))
+    z, _ = ctx.contour_points()
+    t = np.where(br < 2, z.real, cont["t_min"])
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ep = np.abs(prev - fixed)
+    en = np.abs(start - fixed)
+    regions = {}
+    names = "ULM"
+    for a in range(3):
+        for b in range(3):
+            m = (br[ii] == a) & (br[jj] == b)
+            regions[names[a] + names[b]] = m
+    regions["near_diag"] = np.abs(ii - jj) <= 2
+    regions["pre_field"] = np.maximum(t[ii], t[jj]) <= 0
+    regions["turning"] = (t[ii] > cont["t_max"] - 1) & (t[jj] > cont["t_max"] - 1)
+    return {k: [float(ep[m].max()) if m.any() else 0.0,
+                float(en[m].max()) if m.any() else 0.0] for k, m in regions.items()}
+
+
 def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
-                   precision=fkdmft.FK_FP64, log=None):
+                   mixed=True, log=None):
     """Iterations to tol at (U, E) from Sigma = 0, from the converged Sigma of
     E - dE (previous field) and from the network's proposal on it (judged, with
-    the previous field as fallback).  Also checks that the three fixed points
-    agree."""
+    the previous field as fallback), all in FP64, and the network's start in
+    the mixed-precision loop.  Also reports the distance of both warm starts
+    from the fixed point (max and RMS over pairs) and checks that every run
+    reaches the same fixed point."""
     torch = _torch()
     out = dict(U=u, E=e, tol=tol)
     with fkdmft.Context(**cont, U=u, E=e - FIELD_STEP, n_eps=n_eps, n_ebar=n_ebar) as c:
-        r = c.iterate(max_iter, tol=tol, precision=precision)
+        r = c.iterate(max_iter, tol=tol)
         prev = torch.empty((c.n_c, c.n_c), dtype=torch.complex128, device="cuda")
         c.get_sigma(prev)
         out["prev_field_iters"] = r["iters"]
+        out["n_c"] = c.n_c
     glocs = {}
-    for start in ("zero", "previous", "network"):
+    starts = ["zero", "previous", "network"] + (["network_mixed"] if mixed else [])
+    fixed = None
+    for start in starts:
         with fkdmft.Context(**cont, U=u, E=e, n_eps=n_eps, n_ebar=n_ebar) as c:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if start == "zero":
-                r = c.iterate(max_iter, tol=tol, precision=precision)
+                r = c.iterate(max_iter, tol=tol)
             elif start == "previous":
                 c.set_sigma(prev)
-                r = c.iterate(max_iter, tol=tol, precision=precision)
+                r = c.iterate(max_iter, tol=tol)
             else:
-                out["propose_s"] = ws.propose(c, cont, prev, u, e)
-                r = c.iterate_judged(prev, max_iter, tol=tol, accept=accept,
-                                     precision=precision)
-                out["outcome"] = r["outcome"]
+                out[f"{start}_propose_s"] = ws.propose(c, cont, prev, u, e)
+                if fixed is not None and start == "network":
+                    s0 = c.get_sigma()
+                    p0 = prev.cpu().numpy()
+                    out["start_err_previous"] = [float(np.max(np.abs(p0 - fixed))),
+                                                 float(np.sqrt(np.mean(np.abs(p0 - fixed) ** 2)))]
+                    out["start_err_network"] = [float(np.max(np.abs(s0 - fixed))),
+                                                float(np.sqrt(np.mean(np.abs(s0 - fixed) ** 2)))]
+                    out["start_err_regions"] = _error_regions(c, cont, p0, s0, fixed)
+                prec = fkdmft.FK_MIXED if start == "network_mixed" else fkdmft.FK_FP64
+                r = c.iterate_judged(prev, max_iter, tol=tol, accept=accept, precision=prec)
+                out[f"{start}_outcome"] = r["outcome"]
             torch.cuda.synchronize()
             out[f"{start}_iters"] = r["iters"]
             out[f"{start}_s"] = time.perf_counter() - t0
             out[f"{start}_converged"] = bool(r["converged"])
             glocs[start] = c.get_gloc()
+            if start == "zero":
+                fixed = c.get_sigma()
     ref = glocs["zero"]
     out["gloc_spread"] = max(float(np.max(np.abs(g - ref))) for g in glocs.values())
     if log:
-        log(f"U={u:.3f} E={e:.3f}: zero {out['zero_iters']}, previous "
-            f"{out['previous_iters']}, network {out['network_iters']} "
-            f"(outcome {out['outcome']}), spread {out['gloc_spread']:.1e}")
+        log(f"U={u:.3f} E={e:.3f} N_c={out['n_c']}: iterations zero {out['zero_iters']}, "
+            f"previous {out['previous_iters']}, network {out['network_iters']} "
+            f"(outcome {out['network_outcome']})"
+            + (f", network+mixed {out['network_mixed_iters']}" if mixed else "")
+            + f"; start error max/rms previous {out.get('start_err_previous')}, "
+            f"network {out.get('start_err_network')}; spread {out['gloc_spread']:.1e}")
     return out
+
+
+# ------------------------------------------------------------------ recipes
+# Training contour: t in [-10, 30], beta = 10, dtau = 0.05 with dt = 0.2
+# (N_c = 600) for most field sweeps and dt = 0.1 (N_c = 1000) for the rest, so
+# that the network sees the step size change; evaluation on dt = 0.05
+# (N_c = 1800).
+TRAIN_CONTOURS = (dict(t_min=-10.0, t_max=30.0, dt=0.2, dtau=0.05, beta=10.0),
+                  dict(t_min=-10.0, t_max=30.0, dt=0.1, dtau=0.05, beta=10.0))
+EVAL_CONTOUR = dict(t_min=-10.0, t_max=30.0, dt=0.05, dtau=0.05, beta=10.0)
+FIELDS = tuple(0.5 + FIELD_STEP * k for k in range(15))        # 0.5 .. 4.0
+
+
+def _main(argv=None):
+    import argparse
+    import json
+    import os
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    tr = sub.add_parser("train", help="generate field sweeps, train, save")
+    tr.add_argument("--out", required=True)
+    tr.add_argument("--n-u", type=int, nargs=2, default=[60, 16],
+                    help="U values per training contour")
+    tr.add_argument("--u-range", type=float, nargs=2, default=[0.25, 1.75])
+    tr.add_argument("--gh", type=int, default=10)
+    tr.add_argument("--tol", type=float, default=1e-6)
+    tr.add_argument("--rows", type=int, default=4096)
+    tr.add_argument("--steps", type=int, nargs=3, default=[15000, 10000, 5000])
+    tr.add_argument("--lrs", type=float, nargs=3, default=[3e-4, 1e-4, 3e-5])
+    tr.add_argument("--batch", type=int, default=8192)
+    tr.add_argument("--seed", type=int, default=1)
+    ev = sub.add_parser("evaluate", help="compare starts on unseen (U, E)")
+    ev.add_argument("--weights", required=True)
+    ev.add_argument("--out", required=True)
+    ev.add_argument("--cases", type=float, nargs="+",
+                    default=[0.6, 1.3, 1.1, 2.05, 1.45, 3.3])
+    ev.add_argument("--gh", type=int, default=15)
+    ev.add_argument("--tol", type=float, default=1e-8)
+    a = ap.parse_args(argv)
+
+    def log(*m):
+        print(*m, flush=True)
+
+    if a.cmd == "train":
+        torch = _torch()
+        rng = np.random.default_rng(a.seed)
+        xs, ts, stats = [], [], []
+        t0 = time.perf_counter()
+        for cont, n_u in zip(TRAIN_CONTOURS, a.n_u):
+            us = np.sort(rng.uniform(a.u_range[0], a.u_range[1], n_u))
+            log(f"contour dt={cont['dt']}: {n_u} values of U")
+            x, t, st = field_sweep_data(cont, list(us), list(FIELDS), a.gh, a.gh, a.tol,
+                                        a.rows, seed=int(rng.integers(1 << 31)),
+                                        max_iter=100, log=log)
+            xs.append(x)
+            ts.append(t)
+            stats.append(dict(dt=cont["dt"], U=[float(u) for u in us], fields=st))
+        x, t = torch.cat(xs), torch.cat(ts)
+        gen_s = time.perf_counter() - t0
+        log(f"data: {x.shape[0]} rows in {gen_s:.0f} s")
+        t0 = time.perf_counter()
+        ws, hist = train(x, t, steps=tuple(a.steps), lrs=tuple(a.lrs), batch=a.batch,
+                         seed=a.seed, log=log)
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        ws.save(a.out)
+        runs = sum(len(f["iters"]) for s in stats for f in s["fields"])
+        pairs = x.shape[0] // a.rows
+        with open(os.path.splitext(a.out)[0] + "_train.json", "w") as f:
+            json.dump(dict(runs=runs, pairs=pairs, rows=int(x.shape[0]), gen_s=gen_s,
+                           train_s=time.perf_counter() - t0, t_rms=ws.t_rms,
+                           loss_first=float(hist[0]),
+                           loss_last=float(np.mean(hist[-100:])), gh=a.gh, tol=a.tol,
+                           sweeps=stats), f, indent=1)
+        log(f"saved {a.out}: {runs} runs, {pairs} pairs")
+    else:
+        ws = WarmStart.load(a.weights)
+        res = []
+        for u, e in zip(a.cases[0::2], a.cases[1::2]):
+            res.append(compare_starts(ws, EVAL_CONTOUR, u, e, a.gh, a.gh, a.tol, log=log))
+            with open(a.out, "w") as f:
+                json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    _main()

@@ -601,3 +601,19 @@ def test_adam_first_step_moves_every_parameter_by_lr():
     _, g = mlp.loss_and_grad(p, shapes, x[r], t[r])
     big = np.abs(g) > 1e-4
     assert np.allclose((p - p1)[big], 1e-3 * np.sign(g[big]), rtol=1e-3, atol=0)
+
+
+def test_m_matrix_matches_printed_display():
+    """The oracle's point-split operator M equals the paper's printed M display
+    (Sec. II) entry by entry, written out by hand in tests/golden for N_t = 2,
+    N_tau = 3, dt = 0.5, dtau = 0.25, mu = 0.4."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "m_display_small.txt")
+    want = np.zeros((7, 7), complex)
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            r, c, re, im = line.split()
+            want[int(r), int(c)] = float(re) + 1j * float(im)
+    z, w = contour.points(0.0, 1.0, 0.5, 0.25, 0.75)
+    assert len(w) == 7
+    assert np.max(np.abs(contour.m_matrix(w, 0.4) - want)) < 1e-15
