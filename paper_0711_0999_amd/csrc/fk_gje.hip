@@ -333,37 +333,41 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       Bo[e] = t;
     }
     __syncthreads();
-    // ---- rank-iw update of the other column groups of the panel.  Work unit:
-    // one row and one group of kIB columns; its 2 kIB loads go out together.
-    const int og = ngroups - 1;
+    // ---- rank-iw update of the other column groups of the panel on the rows
+    // this thread owns and has just written: each row's eliminated values are
+    // read back once (same thread, program order) and applied to every other
+    // group of the row.
     const int cur = b0 / kIB;
-    const int units = n * og;
     int pv0[kIB];
 #pragma unroll
     for (int l = 0; l < kIB; ++l) pv0[l] = (l < iw) ? pvt[l] : -1;
-    for (int u = tid; u < units; u += kPanelThreads) {
-      const int r = u / og;
-      int g = u - r * og;
-      g += (g >= cur) ? 1 : 0;
-      const int cg = g * kIB, gw = min(kIB, cw - cg);
-      cplx<T> mm[kIB], od[kIB];
-#pragma unroll
-      for (int l = 0; l < kIB; ++l)
-        mm[l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
-#pragma unroll
-      for (int cc = 0; cc < kIB; ++cc)
-        od[cc] = x[(size_t)r * ld + c0 + cg + min(cc, gw - 1)];
+#pragma unroll 1
+    for (int i = 0; i < kRPT; ++i) {
+      const int r = tid + i * kPanelThreads;
+      if (r >= n) continue;
       bool isp = false;
 #pragma unroll
       for (int l = 0; l < kIB; ++l) isp |= (pv0[l] == r);
+      cplx<T> mm[kIB];
 #pragma unroll
-      for (int cc = 0; cc < kIB; ++cc) {
-        cplx<T> acc = od[cc];
-        if (isp) acc.re = acc.im = T(0);
+      for (int l = 0; l < kIB; ++l) mm[l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
+#pragma unroll 1
+      for (int g = 0; g < ngroups; ++g) {
+        if (g == cur) continue;
+        const int cg = g * kIB, gw = min(kIB, cw - cg);
+        cplx<T> od[kIB];
 #pragma unroll
-        for (int l = 0; l < kIB; ++l)
-          if (l < iw) cfma(acc, mm[l], Bo[l * kNB + cg + cc]);
-        if (cc < gw) x[(size_t)r * ld + c0 + cg + cc] = acc;
+        for (int cc = 0; cc < kIB; ++cc)
+          od[cc] = x[(size_t)r * ld + c0 + cg + min(cc, gw - 1)];
+#pragma unroll
+        for (int cc = 0; cc < kIB; ++cc) {
+          cplx<T> acc = od[cc];
+          if (isp) acc.re = acc.im = T(0);
+#pragma unroll
+          for (int l = 0; l < kIB; ++l)
+            if (l < iw) cfma(acc, mm[l], Bo[l * kNB + cg + cc]);
+          if (cc < gw) x[(size_t)r * ld + c0 + cg + cc] = acc;
+        }
       }
     }
     __syncthreads();
