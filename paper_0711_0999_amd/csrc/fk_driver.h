@@ -87,6 +87,29 @@ template <typename T> void batch_free(Batch<T>& b) {
   b = Batch<T>();
 }
 
+// Update work items of matrix m for outer step S: pass 0 the next block's
+// column tiles (narrow launch), pass 1 every column tile outside the current
+// and next blocks (big launch).  Items are ordered in bands of kSwz column
+// tiles, rows outer within a band, so the workgroups in flight on one XCD
+// (consecutive items) share both their pivot-block rows and their B columns
+// in its L2.
+constexpr int kSwz = 8;
+inline void push_tiles(std::vector<TileItem>& it, int m, int nt, int ntr, int S,
+                       int pass) {
+  std::vector<int> cols;
+  for (int tc = 0; tc < nt; ++tc) {
+    const int blk = tc / (kNBO / kTile);
+    const bool narrow = blk == S + 1;
+    const bool big = blk != S && blk != S + 1;
+    if (pass == 0 ? narrow : big) cols.push_back(tc);
+  }
+  for (size_t c0 = 0; c0 < cols.size(); c0 += kSwz) {
+    const size_t c1 = std::min(cols.size(), c0 + kSwz);
+    for (int tr = 0; tr < ntr; ++tr)
+      for (size_t c = c0; c < c1; ++c) it.push_back(TileItem{m, (short)tr, (short)cols[c]});
+  }
+}
+
 template <typename T>
 hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
   batch_free(b);
@@ -128,15 +151,9 @@ hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
       (pass ? b.offB : b.offN)[S] = (int)it.size();
       int per = 0;
       for (int m = 0; m < cap; ++m) {
-        per = 0;
-        for (int tc = 0; tc < nt; ++tc) {
-          const int blk = tc / (kNBO / kTile);
-          const bool narrow = blk == S + 1;
-          const bool big = blk != S && blk != S + 1;
-          if (pass == 0 ? !narrow : !big) continue;
-          for (int tr = 0; tr < ntr; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
-          per += ntr;
-        }
+        const size_t before = it.size();
+        push_tiles(it, m, nt, ntr, S, pass);
+        per = (int)(it.size() - before);
       }
       (pass ? b.cntB : b.cntN)[S] = per;
     }
@@ -214,13 +231,7 @@ hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
         if (S * kNBO >= n[m]) continue;
         const int nt = (n[m] + kTile - 1) / kTile;
         const int ntr = (n[m] + tile_rows(b.variant) - 1) / tile_rows(b.variant);
-        for (int tc = 0; tc < nt; ++tc) {
-          const int blk = tc / (kNBO / kTile);
-          const bool narrow = blk == S + 1;
-          const bool big = blk != S && blk != S + 1;
-          if (pass == 0 ? !narrow : !big) continue;
-          for (int tr = 0; tr < ntr; ++tr) it.push_back(TileItem{m, (short)tr, (short)tc});
-        }
+        push_tiles(it, m, nt, ntr, S, pass);
       }
       (pass ? b.totB : b.totN)[S] = (int)it.size() - (pass ? b.offB : b.offN)[S];
     }

@@ -70,6 +70,7 @@ class WarmStart:
     """The network and the target normalization it was trained with."""
 
     def __init__(self, params=None, t_rms=1.0, seed=0):
+        _torch()                      # torch's device first, then the library's
         self.net = fkdmft.MLP(D_IN, WIDTH, DEPTH, D_OUT, params=params, seed=seed)
         self.t_rms = float(t_rms)
 
