@@ -182,6 +182,11 @@ __device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, in
   }
 }
 
+// Column groups updated per batch of loads in the panel's rank-kIB updates
+// (bounded by registers: kIB complex values per group).
+template <typename T> struct GroupBatch { static constexpr int value = 4; };
+template <> struct GroupBatch<float> { static constexpr int value = 7; };
+
 // ---------------------------------------------------- panel: factorization
 // Eliminate the columns of inner panel q (all rows) with partial pivoting.
 template <typename T>
@@ -197,6 +202,7 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c0 = q * kNB, cw = min(kNB, n - c0);
   const T inf_key = big_value<T>();
+  constexpr int kGB = GroupBatch<T>::value;
 
   bool pvd[kRPT];
 #pragma unroll
@@ -351,22 +357,37 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       cplx<T> mm[kIB];
 #pragma unroll
       for (int l = 0; l < kIB; ++l) mm[l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
+      // the other groups in batches of kGB whose loads are all in flight
+      // together (a group index past the panel reads the current group and
+      // stores nothing)
 #pragma unroll 1
-      for (int g = 0; g < ngroups; ++g) {
-        if (g == cur) continue;
-        const int cg = g * kIB, gw = min(kIB, cw - cg);
-        cplx<T> od[kIB];
+      for (int q0 = 0; q0 < kNB / kIB - 1; q0 += kGB) {
+        cplx<T> od[kGB][kIB];
+        int cgs[kGB], gws[kGB];
+        bool ok[kGB];
 #pragma unroll
-        for (int cc = 0; cc < kIB; ++cc)
-          od[cc] = x[(size_t)r * ld + c0 + cg + min(cc, gw - 1)];
+        for (int q = 0; q < kGB; ++q) {
+          int g = q0 + q;
+          g += (g >= cur) ? 1 : 0;
+          ok[q] = (q0 + q < kNB / kIB - 1) && g < ngroups;
+          cgs[q] = (ok[q] ? g : cur) * kIB;
+          gws[q] = min(kIB, cw - cgs[q]);
 #pragma unroll
-        for (int cc = 0; cc < kIB; ++cc) {
-          cplx<T> acc = od[cc];
-          if (isp) acc.re = acc.im = T(0);
+          for (int cc = 0; cc < kIB; ++cc)
+            od[q][cc] = x[(size_t)r * ld + c0 + cgs[q] + min(cc, gws[q] - 1)];
+        }
 #pragma unroll
-          for (int l = 0; l < kIB; ++l)
-            if (l < iw) cfma(acc, mm[l], Bo[l * kNB + cg + cc]);
-          if (cc < gw) x[(size_t)r * ld + c0 + cg + cc] = acc;
+        for (int q = 0; q < kGB; ++q) {
+          if (!ok[q]) continue;
+#pragma unroll
+          for (int cc = 0; cc < kIB; ++cc) {
+            cplx<T> acc = od[q][cc];
+            if (isp) acc.re = acc.im = T(0);
+#pragma unroll
+            for (int l = 0; l < kIB; ++l)
+              if (l < iw) cfma(acc, mm[l], Bo[l * kNB + cgs[q] + cc]);
+            if (cc < gws[q]) x[(size_t)r * ld + c0 + cgs[q] + cc] = acc;
+          }
         }
       }
     }
