@@ -7,7 +7,8 @@ batched inversion, rho-weighted reduction, current) plus the impurity update.
 Inputs are the physical parameters only (synthetic, resident on the device).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--U 1.0]
-                [--mixed] [--converge] [--no-cpu-baseline] [--workload c2|c1]
+                [--mixed] [--converge | --no-converge] [--no-cpu-baseline]
+                [--workload c2|c1]
 Prints ONE JSON line.
 """
 import argparse
@@ -77,6 +78,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-converge", action="store_true")
     ap.add_argument("--tune-bytes", type=float, default=48 * 2 ** 30)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -204,22 +206,36 @@ def main():
             }
             log(f"bench: mixed ir={ir} done")
         out["mixed"] = mixed
-    if args.converge:
-        for name, p2, ir in (("fp64", fkdmft.FK_FP64, 0), ("mixed_switch", fkdmft.FK_MIXED, 0)):
-            ctx2 = fkdmft.Context(stream=stream, **w.kwargs())
-            t_now = ctx.get_tuning()
-            ctx2.set_tuning(tile_rows=t_now["tile_rows"], batch=t_now["batch"],
-                            lookahead=t_now["lookahead"])
-            ctx2.set_refinement(ir)
+    # iterations to delta < 1e-8 from Sigma = 0, FP64 and the precision-switching
+    # mixed loop.  The default run uses the same contour with 15 x 15 points
+    # (the iteration count is a property of the contour and the model; the
+    # quadrature order changes it little); --converge runs the full grid.
+    conv_kw = dict(w.kwargs())
+    if not args.converge:
+        conv_kw.update(n_eps=15, n_ebar=15)
+    if not args.no_converge:
+        conv = {"points": conv_kw["n_eps"] * conv_kw["n_ebar"], "tol": configs.C2_TOL}
+        for name, p2 in (("fp64", fkdmft.FK_FP64), ("mixed_switch", fkdmft.FK_MIXED)):
+            ctx2 = fkdmft.Context(stream=stream, **conv_kw)
+            if args.converge:
+                t_now = ctx.get_tuning()
+                ctx2.set_tuning(tile_rows=t_now["tile_rows"], batch=t_now["batch"],
+                                lookahead=t_now["lookahead"])
+            ctx2.set_refinement(0)
+            ctx2.compute_gloc(fkdmft.FK_FP64)     # allocations outside the timing
+            ctx2.compute_gloc(fkdmft.FK_MIXED)
+            ctx2.set_sigma(np.zeros((ctx2.n_c, ctx2.n_c), np.complex128))
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             r = ctx2.iterate(200, tol=configs.C2_TOL, precision=p2)
             torch.cuda.synchronize()
-            out.setdefault("converge", {})[name] = {
-                "iters": r["iters"], "delta": r["delta"], "converged": r["converged"],
-                "seconds": time.perf_counter() - t2}
-            log(f"bench: converge {name}: {r['iters']} iterations")
+            dt2 = time.perf_counter() - t2
+            conv[name] = {"iters": r["iters"], "delta": r["delta"],
+                          "converged": r["converged"], "seconds": dt2,
+                          "sec_per_iter": dt2 / max(r["iters"], 1)}
+            log(f"bench: converge {name}: {r['iters']} iterations in {dt2:.1f} s")
             ctx2.close()
+        out["converge"] = conv
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -289,10 +289,14 @@ fk_status fk_ws_sketch(fk_ctx* ctx, const double* sigma_dev, int rank,
  *   glob[n_glob] | branch one-hot of i (3), of j (3) | t_i/T, tau_i/beta,
  *   t_j/T, tau_j/beta | [i >= j] | [i - j >= 2] | (t_i - t_j)/T |
  *   max(t_i,t_j,0)/T | sin E t_i+, cos E t_i+, sin E t_j+, cos E t_j+ |
- *   scale*Re, scale*Im of Sigma_prev(i,j) | zero padding to d_in.
+ *   scale*Re, scale*Im of Sigma_prev(i,j) |
+ *   sin(pi k t_i/T), cos(pi k t_i/T) for k = 1..8 | the same for t_j |
+ *   sin(pi k tau_i/beta), cos(pi k tau_i/beta) for k = 1, 2 | the same for
+ *   tau_j | zero padding to d_in   (t = 0 on the imaginary branch, tau = 0 on
+ *   the real ones).
  * d_in >= n_glob + FK_WS_FEATURES, else FK_EINVAL.  A pair index outside
  * [0, N_c^2) yields a row of NaN (fk_ws_targets: a NaN target). */
-#define FK_WS_FEATURES 20
+#define FK_WS_FEATURES 60
 fk_status fk_ws_features(fk_ctx* ctx, const double* sigma_prev_dev,
                          const float* glob_host, int n_glob,
                          const long long* idx_dev, long long rows, double scale,

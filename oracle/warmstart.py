@@ -11,13 +11,15 @@ and 0 on the imaginary branch.  Feature row:
     t_i/T, tau_i/beta, t_j/T, tau_j/beta | [i >= j] | [i - j >= 2] |
     (t_i - t_j)/T | max(t_i, t_j, 0)/T |
     sin E t_i+, cos E t_i+, sin E t_j+, cos E t_j+ |
-    s Re Sigma_prev(i, j), s Im Sigma_prev(i, j) | zeros up to d_in
+    s Re Sigma_prev(i, j), s Im Sigma_prev(i, j) |
+    sin, cos(pi k t_i/T) for k = 1..8 | the same for t_j |
+    sin, cos(pi k tau_i/beta) for k = 1, 2 | the same for tau_j | zeros up to d_in
 where t is Re z on the real branches (0 on the imaginary one) and tau = -Im z
 on the imaginary branch (0 on the real ones).
 """
 import numpy as np
 
-N_FEATURES = 20
+N_FEATURES = 60
 
 
 def branch(n_c, n_t):
@@ -44,6 +46,10 @@ def features(z, n_t, t_span, beta, e_field, sigma_prev, glob, idx, scale, d_in):
         f += [np.sin(pi), np.cos(pi), np.sin(pj), np.cos(pj)]
         s = sigma_prev[i, j]
         f += [scale * s.real, scale * s.imag]
+        for xv, kmax in ((t[i] / t_span, 8), (t[j] / t_span, 8),
+                         (tau[i] / beta, 2), (tau[j] / beta, 2)):
+            for k in range(1, kmax + 1):
+                f += [np.sin(np.pi * k * xv), np.cos(np.pi * k * xv)]
         assert len(f) == ng + N_FEATURES
         rows[r, :len(f)] = f
     return rows

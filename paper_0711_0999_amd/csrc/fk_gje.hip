@@ -475,24 +475,14 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
     const cplx<T>* bm = bbuf + d.boff;
     const int* rowcol = rowcolbuf + d.ioff;
 
-    // C tile and pivot-row mask
+    // pivot-row mask (the C tile itself is read during the last K chunk and
+    // added in the epilogue, so the MFMAs start as soon as chunk 0 is in LDS)
     int rcv[2][4];
-    cplx<T> cv[2][2][4];
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         rcv[ii][v] = rowcol[min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1)];
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1);
-          const int col = min(c0 + 32 * wc + 16 * jj + li, n - 1);
-          cv[ii][jj][v] = xm[(size_t)row * ld + col];
-        }
     // chunk 0
     cplx<T> pa[kLA], pb[kLB];
 #pragma unroll
@@ -514,12 +504,8 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
       for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
-          const int col = c0 + 32 * wc + 16 * jj + li;
-          const int rc = rcv[ii][v];
-          const bool keep = row < n && col < n && !(rc >= J0 && rc < J0 + wO);
-          cr[ii][jj][v] = keep ? cv[ii][jj][v].re : T(0);
-          ci[ii][jj][v] = keep ? cv[ii][jj][v].im : T(0);
+          cr[ii][jj][v] = T(0);
+          ci[ii][jj][v] = T(0);
         }
 #pragma unroll
     for (int t = 0; t < kLA; ++t) {
@@ -539,24 +525,8 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
     }
     __syncthreads();
 
-    for (int kc = 0; kc < nch; ++kc) {
-      const int buf = kc & 1;
-      const bool more = kc + 1 < nch;
-      const int kb = (kc + 1) * kKC;
-      if (more) {
-#pragma unroll
-        for (int t = 0; t < kLA; ++t) {
-          const int e = tid + t * NT;
-          const int i = e / kKC, k = e % kKC;
-          pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(kb + k, wO - 1)];
-        }
-#pragma unroll
-        for (int t = 0; t < kLB; ++t) {
-          const int e = tid + t * NT;
-          const int k = e / kTile, c = e % kTile;
-          pb[t] = bm[(size_t)min(kb + k, wO - 1) * ld + min(c0 + c, n - 1)];
-        }
-      }
+    // the MFMAs of one K chunk from LDS buffer buf
+    auto mfma_chunk = [&](int buf) {
       const cplx<T>* as = As[buf];
       const cplx<T>* bs = Bsh[buf];
 #pragma unroll
@@ -590,26 +560,56 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
             ci[ii][jj] = Mfma<T>::run(ai[ii], br[jj], ci[ii][jj]);
           }
       }
-      if (more) {
+    };
+
+    for (int kc = 0; kc + 1 < nch; ++kc) {
+      const int buf = kc & 1;
+      const int kb = (kc + 1) * kKC;
 #pragma unroll
-        for (int t = 0; t < kLA; ++t) {
-          const int e = tid + t * NT;
-          const int i = e / kKC, k = e % kKC;
-          cplx<T> v = pa[t];
-          if (!(r0 + i < n && kb + k < wO)) v.re = v.im = T(0);
-          As[buf ^ 1][i * AP + k] = v;
-        }
+      for (int t = 0; t < kLA; ++t) {
+        const int e = tid + t * NT;
+        const int i = e / kKC, k = e % kKC;
+        pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(kb + k, wO - 1)];
+      }
 #pragma unroll
-        for (int t = 0; t < kLB; ++t) {
-          const int e = tid + t * NT;
-          const int k = e / kTile, c = e % kTile;
-          cplx<T> v = pb[t];
-          if (!(kb + k < wO && c0 + c < n)) v.re = v.im = T(0);
-          Bsh[buf ^ 1][k * BP + c] = v;
-        }
+      for (int t = 0; t < kLB; ++t) {
+        const int e = tid + t * NT;
+        const int k = e / kTile, c = e % kTile;
+        pb[t] = bm[(size_t)min(kb + k, wO - 1) * ld + min(c0 + c, n - 1)];
+      }
+      mfma_chunk(buf);
+#pragma unroll
+      for (int t = 0; t < kLA; ++t) {
+        const int e = tid + t * NT;
+        const int i = e / kKC, k = e % kKC;
+        cplx<T> v = pa[t];
+        if (!(r0 + i < n && kb + k < wO)) v.re = v.im = T(0);
+        As[buf ^ 1][i * AP + k] = v;
+      }
+#pragma unroll
+      for (int t = 0; t < kLB; ++t) {
+        const int e = tid + t * NT;
+        const int k = e / kTile, c = e % kTile;
+        cplx<T> v = pb[t];
+        if (!(kb + k < wO && c0 + c < n)) v.re = v.im = T(0);
+        Bsh[buf ^ 1][k * BP + c] = v;
       }
       __syncthreads();
     }
+    // last chunk, with the C tile's loads in flight
+    cplx<T> cv[2][2][4];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1);
+          const int col = min(c0 + 32 * wc + 16 * jj + li, n - 1);
+          cv[ii][jj][v] = xm[(size_t)row * ld + col];
+        }
+    mfma_chunk((nch - 1) & 1);
+    __syncthreads();   // LDS free for this workgroup's next item
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
@@ -619,9 +619,11 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
           const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
           const int col = c0 + 32 * wc + 16 * jj + li;
           if (row < n && col < n) {
+            const int rc = rcv[ii][v];
+            const bool keep = !(rc >= J0 && rc < J0 + wO);
             cplx<T> c;
-            c.re = cr[ii][jj][v];
-            c.im = ci[ii][jj][v];
+            c.re = cr[ii][jj][v] + (keep ? cv[ii][jj][v].re : T(0));
+            c.im = ci[ii][jj][v] + (keep ? cv[ii][jj][v].im : T(0));
             xm[(size_t)row * ld + col] = c;
           }
         }

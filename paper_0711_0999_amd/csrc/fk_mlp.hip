@@ -247,9 +247,13 @@ __global__ void k_sketch_adj(const c64* __restrict__ s, const c64* __restrict__ 
 //   [glob (ng) | branch one-hot i (3) | branch one-hot j (3) | t_i/T | tau_i/beta |
 //    t_j/T | tau_j/beta | [i >= j] | [i - j >= 2] | (t_i - t_j)/T |
 //    max(t_i, t_j, 0)/T | sin E t_i+ | cos E t_i+ | sin E t_j+ | cos E t_j+ |
-//    s Re Sigma_prev | s Im Sigma_prev | 0 ...]
+//    s Re Sigma_prev | s Im Sigma_prev |
+//    sin, cos (pi k t_i/T), k = 1..8 | same for t_j | sin, cos (pi k tau_i/beta),
+//    k = 1, 2 | same for tau_j | 0 ...]
 // The second step flag marks where the discrete self-energy of the point-split
 // impurity update jumps across the diagonal, two contour indices below it.
+constexpr int kFourierT = 8, kFourierTau = 2;   // harmonics of t/T and tau/beta
+static_assert(20 + 4 * kFourierT + 4 * kFourierTau == kWsFeatures, "feature count");
 struct FeatGeo {
   const c64* z;       // contour points (device)
   int n, n_t;
@@ -292,6 +296,18 @@ __global__ void k_features(FeatGeo g, const c64* __restrict__ sprev,
     const c64 sp = sprev[p];
     row[c++] = (float)(scale * sp.re);
     row[c++] = (float)(scale * sp.im);
+    // Fourier features of the four coordinates
+    const double xs[4] = {ti / g.tspan, tj / g.tspan, taui / g.beta, tauj / g.beta};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int kmax = a < 2 ? kFourierT : kFourierTau;
+      for (int k = 1; k <= kmax; ++k) {
+        double sn, cs;
+        sincospi(k * xs[a], &sn, &cs);
+        row[c++] = (float)sn;
+        row[c++] = (float)cs;
+      }
+    }
     for (; c < d_in; ++c) row[c] = 0.f;
   }
 }

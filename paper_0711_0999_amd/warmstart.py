@@ -20,7 +20,7 @@ from . import fkdmft
 
 RANK = 32
 N_GLOB = 3 + RANK
-D_IN = 64                     # >= N_GLOB + fk_ws_features' 20 pair features
+D_IN = 96                     # >= N_GLOB + fk_ws_features' 60 pair features
 WIDTH = 512
 DEPTH = 4
 D_OUT = 2
@@ -157,7 +157,7 @@ def field_sweep_data(cont, us, es, n_eps, n_ebar, tol, rows_per_run, seed=0,
     return x[:row], t[:row], stats
 
 
-def train(x, t, steps=(15000, 10000, 5000), lrs=(3e-4, 1e-4, 3e-5), batch=8192,
+def train(x, t, steps=(12000, 8000, 4000), lrs=(1e-3, 3e-4, 1e-4), batch=4096,
           seed=0, log=None):
     """Adam on the sampled pairs (minibatches drawn by the library); the targets
     are divided by their RMS first (host arithmetic on a copy)."""
@@ -204,7 +204,7 @@ def _error_regions(ctx, cont, prev, start, fixed):
 
 
 def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
-                   mixed=True, log=None):
+                   mixed=True, log=None, also_accept=()):
     """Iterations to tol at (U, E) from Sigma = 0, from the converged Sigma of
     E - dE (previous field) and from the network's proposal on it (judged, with
     the previous field as fallback), all in FP64, and the network's start in
@@ -220,7 +220,8 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
         out["prev_field_iters"] = r["iters"]
         out["n_c"] = c.n_c
     glocs = {}
-    starts = ["zero", "previous", "network"] + (["network_mixed"] if mixed else [])
+    starts = (["zero", "previous", "network"] + (["network_mixed"] if mixed else [])
+              + [f"network_accept{a:g}" for a in also_accept])
     fixed = None
     for start in starts:
         with fkdmft.Context(**cont, U=u, E=e, n_eps=n_eps, n_ebar=n_ebar) as c:
@@ -242,7 +243,10 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
                                                 float(np.sqrt(np.mean(np.abs(s0 - fixed) ** 2)))]
                     out["start_err_regions"] = _error_regions(c, cont, p0, s0, fixed)
                 prec = fkdmft.FK_MIXED if start == "network_mixed" else fkdmft.FK_FP64
-                r = c.iterate_judged(prev, max_iter, tol=tol, accept=accept, precision=prec)
+                acc = accept
+                if start.startswith("network_accept"):
+                    acc = float(start[len("network_accept"):])
+                r = c.iterate_judged(prev, max_iter, tol=tol, accept=acc, precision=prec)
                 out[f"{start}_outcome"] = r["outcome"]
             torch.cuda.synchronize()
             out[f"{start}_iters"] = r["iters"]
@@ -258,6 +262,8 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
             f"previous {out['previous_iters']}, network {out['network_iters']} "
             f"(outcome {out['network_outcome']})"
             + (f", network+mixed {out['network_mixed_iters']}" if mixed else "")
+            + "".join(f", accept {a:g}: {out[f'network_accept{a:g}_iters']}"
+                      for a in also_accept)
             + f"; start error max/rms previous {out.get('start_err_previous')}, "
             f"network {out.get('start_err_network')}; spread {out['gloc_spread']:.1e}")
     return out
@@ -288,9 +294,9 @@ def _main(argv=None):
     tr.add_argument("--gh", type=int, default=10)
     tr.add_argument("--tol", type=float, default=1e-6)
     tr.add_argument("--rows", type=int, default=4096)
-    tr.add_argument("--steps", type=int, nargs=3, default=[15000, 10000, 5000])
-    tr.add_argument("--lrs", type=float, nargs=3, default=[3e-4, 1e-4, 3e-5])
-    tr.add_argument("--batch", type=int, default=8192)
+    tr.add_argument("--steps", type=int, nargs=3, default=[12000, 8000, 4000])
+    tr.add_argument("--lrs", type=float, nargs=3, default=[1e-3, 3e-4, 1e-4])
+    tr.add_argument("--batch", type=int, default=4096)
     tr.add_argument("--seed", type=int, default=1)
     ev = sub.add_parser("evaluate", help="compare starts on unseen (U, E)")
     ev.add_argument("--weights", required=True)
@@ -299,6 +305,7 @@ def _main(argv=None):
                     default=[0.6, 1.3, 1.1, 2.05, 1.45, 3.3])
     ev.add_argument("--gh", type=int, default=15)
     ev.add_argument("--tol", type=float, default=1e-8)
+    ev.add_argument("--also-accept", type=float, nargs="*", default=[])
     a = ap.parse_args(argv)
 
     def log(*m):
@@ -339,7 +346,8 @@ def _main(argv=None):
         ws = WarmStart.load(a.weights)
         res = []
         for u, e in zip(a.cases[0::2], a.cases[1::2]):
-            res.append(compare_starts(ws, EVAL_CONTOUR, u, e, a.gh, a.gh, a.tol, log=log))
+            res.append(compare_starts(ws, EVAL_CONTOUR, u, e, a.gh, a.gh, a.tol, log=log,
+                                      also_accept=tuple(a.also_accept)))
             with open(a.out, "w") as f:
                 json.dump(res, f, indent=1)
 

@@ -131,19 +131,19 @@ def test_features_targets_and_apply(lib, use_idx):
         glob = inputs.random_rows(1, 5, seed=16)[0]
         idx = inputs.pair_indices(n, 1001, seed=17) if use_idx else None
         rows = 1001 if use_idx else n * n
-        x = torch.empty((rows, 32), dtype=torch.float32, device="cuda")
+        x = torch.empty((rows, 72), dtype=torch.float32, device="cuda")
         t = torch.empty((rows, 2), dtype=torch.float32, device="cuda")
         di = dev(idx) if use_idx else None
-        c.ws_features(dev(sp), glob, di, rows, 0.7, x, 32)
+        c.ws_features(dev(sp), glob, di, rows, 0.7, x, 72)
         c.ws_targets(dev(sp), dev(sn), di, rows, 0.7, t)
-        xo = ows.features(z, c.n_t, 3.0, 1.3, 1.5, sp, glob.astype(np.float64), idx, 0.7, 32)
+        xo = ows.features(z, c.n_t, 3.0, 1.3, 1.5, sp, glob.astype(np.float64), idx, 0.7, 72)
         assert np.max(np.abs(x.cpu().numpy() - xo)) < 1e-6
         assert relerr(t.cpu().numpy(), ows.targets(sp, sn, idx, 0.7)) < 1e-6
         y = inputs.random_rows(n * n, 2, seed=18)
         c.ws_apply(dev(sp), dev(y), 0.7)
         assert relerr(c.get_sigma(), ows.apply(sp, y.astype(np.float64), 0.7)) < 1e-12
         with pytest.raises(lib.FkError):
-            c.ws_features(dev(sp), glob, di, rows, 0.7, x, 24)   # d_in too small
+            c.ws_features(dev(sp), glob, di, rows, 0.7, x, 64)   # d_in too small
 
 
 def test_judged_loop_accepts_rejects_and_falls_back(lib):

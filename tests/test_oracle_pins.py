@@ -558,15 +558,23 @@ def test_warm_start_feature_rows_by_hand():
     sp = np.zeros((10, 10), complex)
     sp[5, 2] = 0.3 - 0.1j
     sp[1, 3] = -0.25j
-    rows = warmstart.features(z, n_t, 2.0, 1.0, 2.0, sp, [0.7], [52, 99, 13], 2.0, 24)
+    rows = warmstart.features(z, n_t, 2.0, 1.0, 2.0, sp, [0.7], [52, 99, 13], 2.0, 64)
     s1, c1 = np.sin(1.0), np.cos(1.0)
-    want = np.zeros((3, 24))
-    want[0, :21] = [0.7, 0, 1, 0, 1, 0, 0, 0.25, 0, 0, 0, 1, 1, 0.25, 0.25,
-                    s1, c1, 0, 1, 0.6, -0.2]
-    want[1, :21] = [0.7, 0, 0, 1, 0, 0, 1, 0, 0.5, 0, 0.5, 1, 0, 0, 0,
-                    0, 1, 0, 1, 0, 0]
-    want[2, :21] = [0.7, 1, 0, 0, 1, 0, 0, -0.25, 0, 0.25, 0, 0, 0, -0.5, 0.25,
-                    0, 1, s1, c1, 0, -0.5]
+    r2 = np.sqrt(0.5)
+    # sin, cos (pi k x) for k = 1..8 at x = 1/4, 0, -1/4; k = 1, 2 at x = 0, 1/2
+    q = [(r2, r2), (1, 0), (r2, -r2), (0, -1), (-r2, -r2), (-1, 0), (-r2, r2), (0, 1)]
+    f_quarter = [v for pair in q for v in pair]
+    f_minus = [v for (a, b) in q for v in (-a, b)]
+    f_zero8 = [0, 1] * 8
+    f_zero2 = [0, 1] * 2
+    f_half2 = [1, 0, 0, -1]
+    want = np.zeros((3, 64))
+    want[0, :61] = ([0.7, 0, 1, 0, 1, 0, 0, 0.25, 0, 0, 0, 1, 1, 0.25, 0.25,
+                     s1, c1, 0, 1, 0.6, -0.2] + f_quarter + f_zero8 + f_zero2 + f_zero2)
+    want[1, :61] = ([0.7, 0, 0, 1, 0, 0, 1, 0, 0.5, 0, 0.5, 1, 0, 0, 0,
+                     0, 1, 0, 1, 0, 0] + f_zero8 + f_zero8 + f_half2 + f_half2)
+    want[2, :61] = ([0.7, 1, 0, 0, 1, 0, 0, -0.25, 0, 0.25, 0, 0, 0, -0.5, 0.25,
+                     0, 1, s1, c1, 0, -0.5] + f_minus + f_quarter + f_zero2 + f_zero2)
     assert np.max(np.abs(rows - want)) < 1e-15
 
 
