@@ -24,6 +24,14 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel (the big trailing update,
+# fk::k_update<double, 2>, 757-matrix batches of the C2 workload), from the
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs summarized under profiles/, each
+# scaled by the same counter's reading for a plain 256 MiB copy (FETCH_SIZE x
+# 2.00, WRITE_SIZE x 1.00).  Reported only for that kernel and batch size.
+PROFILED_TRAFFIC = {"kernel": "fk::k_update<double, 2>", "batch": 757,
+                    "bytes_per_launch": 83.46e9}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -143,9 +151,12 @@ def main():
     # dominant kernel: the trailing update of each outer block, timed per launch
     achieved = kc["flop"] / (kc["ms"] * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if args.mixed else PEAK_FP64_TFLOPS
-    tile_rows = ctx.get_tuning()["tile_rows"]
+    tuned = ctx.get_tuning()
     kname = (f"fk::k_update<{'float' if args.mixed else 'double'}, "
-             f"{2 if tile_rows == 64 else 4}>")
+             f"{2 if tuned['tile_rows'] == 64 else 4}>")
+    traffic = (PROFILED_TRAFFIC["bytes_per_launch"]
+               if (kname == PROFILED_TRAFFIC["kernel"] and w.name.startswith("C2")
+                   and tuned["batch"] == PROFILED_TRAFFIC["batch"]) else None)
     out = {
         "metric": "sec/DMFT iteration at N_c=1800, FP64 vs mixed @1e-8; iters to converge",
         "value": sec,
@@ -164,7 +175,7 @@ def main():
                    "n_c": n, "points": npts, "precision": "mixed" if args.mixed else "fp64",
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "kernel": kname,
                      "launches": kc["launches"],
                      "flops_per_launch": kc["flop"] / max(kc["launches"], 1),
@@ -230,7 +241,8 @@ def main():
             r = ctx2.iterate(200, tol=configs.C2_TOL, precision=p2)
             torch.cuda.synchronize()
             dt2 = time.perf_counter() - t2
-            conv[name] = {"iters": r["iters"], "delta": r["delta"],
+            conv[name] = {"iters": r["iters"], "complex64_iters": ctx2.low_iterations(),
+                          "delta": r["delta"],
                           "converged": r["converged"], "seconds": dt2,
                           "sec_per_iter": dt2 / max(r["iters"], 1)}
             log(f"bench: converge {name}: {r['iters']} iterations in {dt2:.1f} s")

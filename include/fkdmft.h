@@ -159,12 +159,14 @@ fk_status fk_impurity_update(fk_ctx* ctx, double* max_dsigma_out);
  * FK_OK) or after max_iter iterations (FK_ENOTCONV unless tol <= 0, in which
  * case exactly max_iter iterations run and FK_OK is returned).
  * With FK_MIXED the loop runs complex64 (+ refinement) steps until delta <
- * switch_tol (fk_set_switch, default 1e-5) or delta stops contracting
- * (delta(n) > 0.7 delta(n-1): the complex64 noise floor), FK_FP64 afterwards.
+ * switch_tol (fk_set_switch, default 3e-5, above the complex64 noise floor of
+ * G_loc) or stops contracting (delta(n) > 0.95 delta(n-1)), FK_FP64 afterwards.
  * delta_history (nullable, max_iter doubles) receives delta(n). */
 fk_status fk_iterate(fk_ctx* ctx, int max_iter, double tol, fk_precision prec,
                      int* iters_out, double* delta_out, double* delta_history);
 fk_status fk_set_switch(fk_ctx* ctx, double switch_tol);
+/* Number of complex64 iterations in the last fk_iterate / fk_iterate_judged. */
+fk_status fk_low_iterations(const fk_ctx* ctx, int* n);
 
 /* Per-phase device time of the last fk_compute_gloc / fk_impurity_update in
  * milliseconds (HIP events on the context stream): out[0] build, out[1]

@@ -762,6 +762,7 @@ namespace {
 // contracting (it has reached the complex64 noise floor).
 fk_status iteration(fk_ctx* c, int it, bool* low, double* delta, double* prev_delta,
                     double* hist, double* dsig) {
+  if (*low) c->low_iters++;
   fk_status s = fk_compute_gloc(c, *low ? FK_MIXED : FK_FP64, nullptr);
   if (s != FK_OK) return s;
   if (it > 1) {
@@ -777,7 +778,7 @@ fk_status iteration(fk_ctx* c, int it, bool* low, double* delta, double* prev_de
                            hipMemcpyDeviceToDevice, c->st));
   s = impurity(c, dsig);
   if (s != FK_OK) return s;
-  if (*low && (*delta < c->switch_tol || (it > 2 && *delta > 0.7 * *prev_delta)))
+  if (*low && (*delta < c->switch_tol || (it > 2 && *delta > 0.95 * *prev_delta)))
     *low = false;
   *prev_delta = *delta;
   return FK_OK;
@@ -788,6 +789,7 @@ extern "C" fk_status fk_iterate(fk_ctx* c, int max_iter, double tol,
                                 fk_precision prec, int* iters_out,
                                 double* delta_out, double* hist) {
   if (!c || max_iter < 1) return FK_EINVAL;
+  c->low_iters = 0;
   double delta = std::numeric_limits<double>::infinity();
   double prev_delta = delta;
   bool low = (prec == FK_MIXED);
@@ -812,6 +814,7 @@ extern "C" fk_status fk_iterate_judged(fk_ctx* c, const double* fallback_dev,
                                        double* delta_out, double* hist,
                                        int* outcome) {
   if (!c || max_iter < 2 || !(accept > 0.0)) return FK_EINVAL;
+  c->low_iters = 0;
   const size_t nn = (size_t)c->ci.n_c * c->ci.n_c;
   const c64* fb = reinterpret_cast<const c64*>(fallback_dev);
   fk_status s;
@@ -883,6 +886,12 @@ extern "C" fk_status fk_iterate_judged(fk_ctx* c, const double* fallback_dev,
   if (tol > 0.0 && !(delta < tol))
     return set_err(c, FK_ENOTCONV, "not converged after %d iterations (delta %.3e)",
                    max_iter, delta);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_low_iterations(const fk_ctx* c, int* n) {
+  if (!c || !n) return FK_EINVAL;
+  *n = c->low_iters;
   return FK_OK;
 }
 

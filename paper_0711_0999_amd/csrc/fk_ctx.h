@@ -69,7 +69,8 @@ struct fk_ctx {
   bool have_gloc = false;
   bool have_prev = false;
   int ir_steps = 1;
-  double switch_tol = 1e-5;
+  double switch_tol = 3e-5;
+  int low_iters = 0;               // complex64 iterations of the last loop
   double times[7] = {0, 0, 0, 0, 0, 0, 0};
   hipEvent_t ev[8];
 };

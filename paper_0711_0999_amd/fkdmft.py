@@ -83,6 +83,7 @@ SIGNATURES = {
     "fk_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
+    "fk_low_iterations": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     "fk_set_kernel_clock": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fk_kernel_clock": (ctypes.c_int, [_vp, _dp]),
     "fk_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -324,6 +325,11 @@ class Context:
         t = Tuning()
         self._check(self._lib.fk_get_tuning(self._h, ctypes.byref(t)), "fk_get_tuning")
         return t.as_dict()
+
+    def low_iterations(self):
+        n = ctypes.c_int()
+        self._check(self._lib.fk_low_iterations(self._h, ctypes.byref(n)), "fk_low_iterations")
+        return n.value
 
     def set_kernel_clock(self, on=True):
         self._check(self._lib.fk_set_kernel_clock(self._h, int(on)), "fk_set_kernel_clock")
