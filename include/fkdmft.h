@@ -165,6 +165,12 @@ fk_status fk_impurity_update(fk_ctx* ctx, double* max_dsigma_out);
 fk_status fk_iterate(fk_ctx* ctx, int max_iter, double tol, fk_precision prec,
                      int* iters_out, double* delta_out, double* delta_history);
 fk_status fk_set_switch(fk_ctx* ctx, double switch_tol);
+/* G_k of one quadrature point k (N_c x N_c complex128 values, row-major) as the
+ * last FP64 fk_compute_gloc computed it: available for the points of the last
+ * batch of that step, which stay in the batch buffers (fk_points gives their
+ * (eps, ebar, rho)); otherwise, or after a mixed step, FK_ESTATE.  For parity
+ * checks of single points at full size. */
+fk_status fk_get_point_green(const fk_ctx* ctx, int k, double* g, int on_device);
 /* Number of complex64 iterations in the last fk_iterate / fk_iterate_judged. */
 fk_status fk_low_iterations(const fk_ctx* ctx, int* n);
 

@@ -276,6 +276,9 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
     c->times[6] += elapsed(c->ev[6], c->ev[7]);
   }
   c->times[5] = launches;
+  c->last_nmat = std::min(b.cap, c->npts - (c->npts - 1) / b.cap * b.cap);
+  c->last_k0 = c->npts - c->last_nmat;
+  c->last_prec = sizeof(T) == sizeof(double) ? 0 : 1;
   // non-finite check of G_loc
   HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
   HIPCHK(c, launch_maxabs(c->d_gloc, nullptr, (size_t)n * n, c->d_key, c->st));
@@ -886,6 +889,27 @@ extern "C" fk_status fk_iterate_judged(fk_ctx* c, const double* fallback_dev,
   if (tol > 0.0 && !(delta < tol))
     return set_err(c, FK_ENOTCONV, "not converged after %d iterations (delta %.3e)",
                    max_iter, delta);
+  return FK_OK;
+}
+
+extern "C" fk_status fk_get_point_green(const fk_ctx* cc, int k, double* g,
+                                        int on_device) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c || !g) return FK_EINVAL;
+  if (c->last_prec != 0 || k < c->last_k0 || k >= c->last_k0 + c->last_nmat)
+    return set_err(c, FK_ESTATE,
+                   "point %d is not in the FP64 lattice batch left by the last step "
+                   "(points %d..%d)", k, c->last_k0, c->last_k0 + c->last_nmat - 1);
+  const int n = c->ci.n_c, m = k - c->last_k0;
+  Batch<double>& b = c->b64;
+  c64* dst = on_device ? reinterpret_cast<c64*>(g) : c->d_tmp;
+  HIPCHK(c, launch_unpermute<double>(b.x + b.stride * m, b.stride, b.ld,
+                                     b.piv + (size_t)m * n, b.rowcol + (size_t)m * n,
+                                     n, 1, dst, c->st));
+  if (!on_device)
+    HIPCHK(c, hipMemcpyAsync(g, c->d_tmp, sizeof(c64) * (size_t)n * n,
+                             hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
   return FK_OK;
 }
 

@@ -71,6 +71,8 @@ struct fk_ctx {
   int ir_steps = 1;
   double switch_tol = 3e-5;
   int low_iters = 0;               // complex64 iterations of the last loop
+  int last_k0 = 0, last_nmat = 0;  // points left in the lattice batch
+  int last_prec = -1;              // their precision (0 FP64, 1 mixed)
   double times[7] = {0, 0, 0, 0, 0, 0, 0};
   hipEvent_t ev[8];
 };

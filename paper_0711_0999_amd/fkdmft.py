@@ -84,6 +84,7 @@ SIGNATURES = {
     "fk_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_low_iterations": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "fk_get_point_green": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "fk_set_kernel_clock": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fk_kernel_clock": (ctypes.c_int, [_vp, _dp]),
     "fk_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -325,6 +326,13 @@ class Context:
         t = Tuning()
         self._check(self._lib.fk_get_tuning(self._h, ctypes.byref(t)), "fk_get_tuning")
         return t.as_dict()
+
+    def get_point_green(self, k, out=None):
+        out = np.zeros((self.n_c, self.n_c), np.complex128) if out is None else out
+        p, dev, _ = self._matrix_arg(out, True)
+        self._check(self._lib.fk_get_point_green(self._h, int(k), p, dev),
+                    "fk_get_point_green")
+        return out
 
     def low_iterations(self):
         n = ctypes.c_int()
