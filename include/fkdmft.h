@@ -63,8 +63,10 @@ typedef struct {
  * half-filling convention of the impurity shifts:
  *   convention 0 (symmetric): U (w - 1/2) n, shifts mu0 - mu = +U/2, mu1 - mu = -U/2
  *   convention 1 (paper):     U w n,         shifts mu0 - mu = 0,    mu1 - mu = -U
- * gh_average must be 0 (one n_eps x n_ebar rule; the paper's N/N+1 average
- * is not implemented). */
+ * gh_average 0: one n_eps x n_ebar product rule; 1: the average of the
+ * n_eps x n_ebar and (n_eps + 1) x (n_ebar + 1) rules (the paper's N and N + 1
+ * points, Sec. II quadrature paragraph), points of the first rule first, every
+ * weight halved (n_eps, n_ebar <= 149). */
 typedef struct {
   double U, E, mu, w1;
   int n_eps, n_ebar;

@@ -35,13 +35,15 @@ class Problem:
     n_eps: int = 10
     n_ebar: int = 10
     convention: str = "symmetric"
+    gh_average: bool = False
 
     def grid(self):
         z, w = contour.points(self.t_min, self.t_max, self.dt, self.dtau,
                               self.beta)
         n_t, _, _ = contour.sizes(self.t_min, self.t_max, self.dt, self.dtau,
                                   self.beta)
-        eps, ebar, rho = quadrature.product_grid(self.n_eps, self.n_ebar)
+        grid = quadrature.averaged_grid if self.gh_average else quadrature.product_grid
+        eps, ebar, rho = grid(self.n_eps, self.n_ebar)
         return z, w, n_t, eps, ebar, rho
 
 

@@ -37,3 +37,13 @@ def product_grid(n_eps, n_ebar):
     ebar = np.tile(xb, n_eps)
     rho = np.repeat(wa, n_ebar) * np.tile(wb, n_eps)
     return eps, ebar, rho
+
+
+def averaged_grid(n_eps, n_ebar):
+    """The average of the n_eps x n_ebar and (n_eps + 1) x (n_ebar + 1) product
+    rules (Sec. II, the quadrature paragraph: averaging N and N + 1 points):
+    the points of both rules, the first rule's first, weights halved."""
+    e1, b1, r1 = product_grid(n_eps, n_ebar)
+    e2, b2, r2 = product_grid(n_eps + 1, n_ebar + 1)
+    return (np.concatenate([e1, e2]), np.concatenate([b1, b2]),
+            0.5 * np.concatenate([r1, r2]))

@@ -505,7 +505,8 @@ extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
   if (build_contour(cont, &ci) != FK_OK) return FK_EINVAL;
   if (mod->n_eps < 1 || mod->n_eps > 150 || mod->n_ebar < 1 || mod->n_ebar > 150)
     return FK_EINVAL;
-  if (mod->gh_average != 0) return FK_EINVAL;
+  if (mod->gh_average != 0 && mod->gh_average != 1) return FK_EINVAL;
+  if (mod->gh_average && (mod->n_eps > 149 || mod->n_ebar > 149)) return FK_EINVAL;
   if (mod->convention != 0 && mod->convention != 1) return FK_EINVAL;
   if (!(mod->w1 >= 0.0 && mod->w1 <= 1.0)) return FK_EINVAL;
   if (!std::isfinite(mod->U) || !std::isfinite(mod->E) || !std::isfinite(mod->mu))
@@ -523,17 +524,26 @@ extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
   c->ci = ci;
   const int n = ci.n_c, n_t = ci.n_t;
 
-  // quadrature points k = a * n_ebar + b
-  std::vector<double> xa(mod->n_eps), wa(mod->n_eps), xb(mod->n_ebar), wb(mod->n_ebar);
-  fk_gauss_hermite(mod->n_eps, xa.data(), wa.data());
-  fk_gauss_hermite(mod->n_ebar, xb.data(), wb.data());
-  c->npts = mod->n_eps * mod->n_ebar;
-  for (int a = 0; a < mod->n_eps; ++a)
-    for (int b = 0; b < mod->n_ebar; ++b) {
-      c->eps.push_back(xa[a]);
-      c->ebar.push_back(xb[b]);
-      c->rho.push_back(wa[a] * wb[b]);
-    }
+  // quadrature points k = a * n_ebar + b of the n_eps x n_ebar product rule;
+  // with gh_average the (n_eps + 1) x (n_ebar + 1) rule follows, and every
+  // weight is halved: the average of the two rules (Sec. II, the quadrature
+  // paragraph: N and N + 1 points)
+  const int nrules = mod->gh_average ? 2 : 1;
+  c->npts = 0;
+  for (int q = 0; q < nrules; ++q) {
+    const int na = mod->n_eps + q, nb = mod->n_ebar + q;
+    std::vector<double> xa(na), wa(na), xb(nb), wb(nb);
+    fk_gauss_hermite(na, xa.data(), wa.data());
+    fk_gauss_hermite(nb, xb.data(), wb.data());
+    const double scale = nrules == 2 ? 0.5 : 1.0;
+    for (int a = 0; a < na; ++a)
+      for (int b = 0; b < nb; ++b) {
+        c->eps.push_back(xa[a]);
+        c->ebar.push_back(xb[b]);
+        c->rho.push_back(scale * wa[a] * wb[b]);
+      }
+    c->npts += na * nb;
+  }
 
   // antiderivative tables alpha, gamma of the band phase (eq.
   // g_contour_non_final2): sin(Et)/E and (cos Et - 1)/E for real t > 0,

@@ -181,11 +181,12 @@ class Context:
     """One fk_ctx.  stream: a torch.cuda.Stream, an int hipStream_t, or None."""
 
     def __init__(self, t_min, t_max, dt, dtau, beta, U, E, mu=0.0, w1=0.5,
-                 n_eps=10, n_ebar=10, convention="symmetric", stream=None):
+                 n_eps=10, n_ebar=10, convention="symmetric", stream=None,
+                 gh_average=False):
         lib = library()
         self._lib = lib
         c = Contour(t_min, t_max, dt, dtau, beta)
-        m = Model(U, E, mu, w1, n_eps, n_ebar, CONVENTION[convention], 0)
+        m = Model(U, E, mu, w1, n_eps, n_ebar, CONVENTION[convention], int(gh_average))
         if stream is None:
             sp = None
         elif isinstance(stream, int):
@@ -429,7 +430,8 @@ class Batch:
             cs[i] = Contour(kw["t_min"], kw["t_max"], kw["dt"], kw["dtau"], kw["beta"])
             ms[i] = Model(kw["U"], kw["E"], kw.get("mu", 0.0), kw.get("w1", 0.5),
                           kw.get("n_eps", 10), kw.get("n_ebar", 10),
-                          CONVENTION[kw.get("convention", "symmetric")], 0)
+                          CONVENTION[kw.get("convention", "symmetric")],
+                          int(kw.get("gh_average", False)))
         h = _vp()
         s = lib.fk_batch_create(n, cs, ms, ctypes.byref(h))
         if s != FK_OK:

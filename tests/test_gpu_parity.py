@@ -198,3 +198,23 @@ def test_autotune_picks_a_valid_schedule(lib):
     assert t["est_step_ms"] > 0
     ctx.compute_gloc()
     assert relerr(ctx.get_gloc(), ref.get_gloc()) < 1e-13
+
+
+def test_averaged_quadrature_lattice_step(lib):
+    """gh_average = 1: the points of the n x n and (n+1) x (n+1) rules with
+    halved weights (Sec. II quadrature paragraph), against the oracle."""
+    say("case: N / N+1 averaged quadrature, N_c = 73")
+    kw = dict(t_min=-1.0, t_max=2.0, dt=0.1, dtau=0.1, beta=1.3, U=1.0, E=1.5,
+              n_eps=3, n_ebar=4)
+    ctx = lib.Context(gh_average=True, **kw)
+    e, eb, r = ctx.points()
+    assert len(e) == 3 * 4 + 4 * 5 and abs(r.sum() - 1.0) < 1e-14
+    sig = inputs.random_sigma(ctx.n_c, seed=9, scale=0.2)
+    ctx.set_sigma(sig)
+    ctx.compute_gloc()
+    p = dmft.Problem(t_min=-1.0, t_max=2.0, dt=0.1, dtau=0.1, beta=1.3, u=1.0,
+                     e_field=1.5, n_eps=3, n_ebar=4, gh_average=True)
+    go, jo, _ = dmft.lattice_only(p, sig)
+    assert relerr(ctx.get_gloc(), go) < TOL64
+    assert relerr(ctx.get_current()[1], jo) < TOL64
+    ctx.close()

@@ -69,3 +69,11 @@ def test_create_rejects_bad_model(lib):
     with pytest.raises(lib.FkError) as e:
         lib.Context(-5, 5, 0.2, 0.2, 10, 0.5, 1.0, w1=1.5)
     assert e.value.status in (lib.FK_EINVAL, lib.FK_EDEVICE)
+
+
+def test_create_rejects_averaged_rule_beyond_150_points(lib):
+    """The N / N+1 average needs N + 1 <= 150 (the host rule's limit); the
+    check runs before any device call."""
+    with pytest.raises(lib.FkError) as e:
+        lib.Context(-5, 5, 0.2, 0.2, 10, 0.5, 1.0, n_eps=150, n_ebar=10, gh_average=True)
+    assert e.value.status == lib.FK_EINVAL

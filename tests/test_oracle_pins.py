@@ -625,3 +625,25 @@ def test_m_matrix_matches_printed_display():
     z, w = contour.points(0.0, 1.0, 0.5, 0.25, 0.75)
     assert len(w) == 7
     assert np.max(np.abs(contour.m_matrix(w, 0.4) - want)) < 1e-15
+
+
+def test_averaged_quadrature_counts_and_moments():
+    """The N / N+1 average (Sec. II quadrature paragraph): with N = 54 it has
+    the 5941 points the paper quotes (and 20201 with N = 100); weights sum to
+    one; both rules integrate eps^2 ebar^2 exp(-eps^2 - ebar^2)/pi = 1/4 and
+    eps^4 (3/4) exactly, so their average does too; an odd moment vanishes."""
+    for n, count in [(54, 5941), (100, 20201)]:
+        e, b, r = quadrature.averaged_grid(n, n)
+        assert len(e) == count
+    e, b, r = quadrature.averaged_grid(6, 7)
+    assert len(e) == 6 * 7 + 7 * 8
+    assert abs(r.sum() - 1.0) < 1e-14
+    assert abs(np.sum(r * e ** 2 * b ** 2) - 0.25) < 1e-14
+    assert abs(np.sum(r * e ** 4) - 0.75) < 1e-13
+    assert abs(np.sum(r * e ** 3 * b)) < 1e-14
+    # a moment beyond the 6-point rule's exactness (degree 12 > 2*6-1) differs
+    # from the exact 10395/64 for one rule but the average is their mean
+    e1, b1, r1 = quadrature.product_grid(6, 7)
+    e2, b2, r2 = quadrature.product_grid(7, 8)
+    m = lambda ee, rr: np.sum(rr * ee ** 12)
+    assert abs(np.sum(r * e ** 12) - 0.5 * (m(e1, r1) + m(e2, r2))) < 1e-9
