@@ -205,10 +205,11 @@ def _error_regions(ctx, cont, prev, start, fixed):
 
 def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
                    mixed=True, log=None, also_accept=()):
-    """Iterations to tol at (U, E) from Sigma = 0, from the converged Sigma of
-    E - dE (previous field) and from the network's proposal on it (judged, with
-    the previous field as fallback), all in FP64, and the network's start in
-    the mixed-precision loop.  Also reports the distance of both warm starts
+    """Iterations to tol at (U, E) from Sigma = 0, from the equilibrium Sigma
+    (E = 0, same contour), from the converged Sigma of E - dE (previous field)
+    and from the network's proposal on it (judged, with the previous field as
+    fallback), all in FP64, and the network's start in the mixed-precision
+    loop.  Also reports the distance of both warm starts
     from the fixed point (max and RMS over pairs) and checks that every run
     reaches the same fixed point."""
     torch = _torch()
@@ -219,8 +220,16 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
         c.get_sigma(prev)
         out["prev_field_iters"] = r["iters"]
         out["n_c"] = c.n_c
+    # the paper's usual guess: the equilibrium self-energy (E = 0 on the same
+    # contour), independent of the field
+    with fkdmft.Context(**cont, U=u, E=0.0, n_eps=n_eps, n_ebar=n_ebar) as c:
+        r = c.iterate(max_iter, tol=tol)
+        equil = torch.empty((c.n_c, c.n_c), dtype=torch.complex128, device="cuda")
+        c.get_sigma(equil)
+        out["equilibrium_solve_iters"] = r["iters"]
     glocs = {}
-    starts = (["zero", "previous", "network"] + (["network_mixed"] if mixed else [])
+    starts = (["zero", "equilibrium", "previous", "network"]
+              + (["network_mixed"] if mixed else [])
               + [f"network_accept{a:g}" for a in also_accept])
     fixed = None
     for start in starts:
@@ -231,6 +240,9 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
                 r = c.iterate(max_iter, tol=tol)
             elif start == "previous":
                 c.set_sigma(prev)
+                r = c.iterate(max_iter, tol=tol)
+            elif start == "equilibrium":
+                c.set_sigma(equil)
                 r = c.iterate(max_iter, tol=tol)
             else:
                 out[f"{start}_propose_s"] = ws.propose(c, cont, prev, u, e)
@@ -259,6 +271,7 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
     out["gloc_spread"] = max(float(np.max(np.abs(g - ref))) for g in glocs.values())
     if log:
         log(f"U={u:.3f} E={e:.3f} N_c={out['n_c']}: iterations zero {out['zero_iters']}, "
+            f"equilibrium {out['equilibrium_iters']}, "
             f"previous {out['previous_iters']}, network {out['network_iters']} "
             f"(outcome {out['network_outcome']})"
             + (f", network+mixed {out['network_mixed_iters']}" if mixed else "")
