@@ -143,6 +143,11 @@ fk_status fk_set_refinement(fk_ctx* ctx, int ir_steps);
 /* j(t_i), the time t_i = t_min + i dt and (nullable) n(t_i) = Re[-i G^<_loc(t_i,t_i)]
  * from the last lattice step; N_t doubles each.  FK_ESTATE before any step. */
 fk_status fk_get_current(const fk_ctx* ctx, double* t, double* j, double* n_t);
+/* Zeroth spectral moment m0(t_i) = G^>_loc(t_i, t_i) - G^<_loc(t_i, t_i) =
+ * G_loc[2 N_t - i][i] - G_loc[i][2 N_t - i] for i < N_t (the sum rule of the
+ * moments paragraph of Sec. II: -i in the continuum, O(dt) off on the
+ * discrete contour).  m0: 2 N_t doubles (re, im interleaved). */
+fk_status fk_get_zeroth_moment(const fk_ctx* ctx, double* m0);
 
 /* Falicov-Kimball impurity update (eqs. effective_medium, dynamical_mean_field,
  * g_imp_solve and Dyson again), in right-weighted form A -> A W:

@@ -749,16 +749,32 @@ extern "C" fk_status fk_get_current(const fk_ctx* cc, double* t, double* j,
                              hipMemcpyDeviceToHost, c->st));
   }
   if (n_t_out) {
-    // n(t_i) = Re[-i G_loc[i][2 N_t - i]] = Im G_loc[i][2 N_t - i]
-    std::vector<c64> row(1);
-    for (int i = 0; i < n_t; ++i) {
-      HIPCHK(c, hipMemcpyAsync(row.data(), c->d_gloc + (size_t)i * n + (2 * n_t - i),
-                               sizeof(c64), hipMemcpyDeviceToHost, c->st));
-      HIPCHK(c, hipStreamSynchronize(c->st));
-      n_t_out[i] = row[0].im;
-    }
+    // n(t_i) = Re[-i G^<(t_i, t_i)] = Im G_loc[i][2 N_t - i]
+    std::vector<c64> less(n_t);
+    HIPCHK(c, launch_equal_time(c->d_gloc, n_t, n, c->d_tmp, c->d_tmp + n_t, c->st));
+    HIPCHK(c, hipMemcpyAsync(less.data(), c->d_tmp, sizeof(c64) * n_t,
+                             hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (int i = 0; i < n_t; ++i) n_t_out[i] = less[i].im;
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
+  return FK_OK;
+}
+
+extern "C" fk_status fk_get_zeroth_moment(const fk_ctx* cc, double* m0) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c || !m0) return FK_EINVAL;
+  if (!c->have_gloc) return set_err(c, FK_ESTATE, "no lattice step yet");
+  const int n_t = c->ci.n_t, n = c->ci.n_c;
+  std::vector<c64> lg(2 * (size_t)n_t);
+  HIPCHK(c, launch_equal_time(c->d_gloc, n_t, n, c->d_tmp, c->d_tmp + n_t, c->st));
+  HIPCHK(c, hipMemcpyAsync(lg.data(), c->d_tmp, sizeof(c64) * 2 * n_t,
+                           hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (int i = 0; i < n_t; ++i) {   // G^> - G^<
+    m0[2 * i] = lg[n_t + i].re - lg[i].re;
+    m0[2 * i + 1] = lg[n_t + i].im - lg[i].im;
+  }
   return FK_OK;
 }
 

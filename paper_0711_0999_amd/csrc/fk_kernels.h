@@ -42,6 +42,8 @@ hipError_t launch_current(const cplx<TI>* xbuf, size_t mat_stride, int ld,
                           int n, double* cur, hipStream_t st);
 hipError_t launch_maxabs(const c64* a, const c64* b, size_t total,
                          unsigned long long* key, hipStream_t st);
+hipError_t launch_equal_time(const c64* g, int n_t, int n, c64* less, c64* greater,
+                             hipStream_t st);
 hipError_t launch_right_weight(const c64* src, const c64* w, c64* dst, int ld,
                                int n, hipStream_t st);
 hipError_t launch_add_right_weighted(c64* g0inv, const c64* sigma, const c64* w,

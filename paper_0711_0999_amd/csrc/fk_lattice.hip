@@ -177,6 +177,24 @@ __global__ void k_current(const cplx<TI>* __restrict__ xbuf, size_t mat_stride,
   cur[i] += acc;
 }
 
+// Equal-time entries of G_loc: less[i] = G[i][2 N_t - i] (G^<(t_i, t_i)) and
+// greater[i] = G[2 N_t - i][i] (G^>(t_i, t_i)), i < N_t.
+__global__ void k_equal_time(const c64* __restrict__ g, int n_t, int n,
+                             c64* __restrict__ less, c64* __restrict__ greater) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_t) return;
+  const int p = 2 * n_t - i;
+  less[i] = g[(size_t)i * n + p];
+  greater[i] = g[(size_t)p * n + i];
+}
+
+hipError_t launch_equal_time(const c64* g, int n_t, int n, c64* less, c64* greater,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_equal_time, dim3((n_t + 127) / 128), dim3(128), 0, st, g, n_t,
+                     n, less, greater);
+  return hipGetLastError();
+}
+
 // -------------------------------------------------------------- norms ------
 // bits of the max of |a - b| (or |a| when b == nullptr) as an unsigned 64-bit
 // key: non-negative doubles order like their bit patterns, NaN above +Inf.

@@ -1,0 +1,58 @@
+"""Extrapolation of the discrete results to zero time step.
+
+The paper extrapolates its dt-dependent results with Lagrange polynomials in
+dt (Sec. II, the accuracy discussion of the results).  Here several contours
+that differ only in the step h (dt = dtau = h) are solved together in one
+multi-instance sweep (uneven N_c in shared batched launches, fk_batch); the
+current j(t), the filling n(t) and the zeroth moment m0(t) are read on the
+coarsest time grid, and their value at h = 0 is the Lagrange combination
+sum_k w_k f_k with w_k = prod_{m != k} h_m / (h_m - h_k).  The extrapolation is
+host arithmetic on a few vectors of N_t values; every DMFT step runs in the
+library's kernels.
+"""
+import numpy as np
+
+from . import fkdmft
+
+
+def lagrange_weights(hs):
+    """w_k with sum_k w_k f(h_k) = p(0) for the polynomial p through the points."""
+    hs = np.asarray(hs, dtype=np.float64)
+    w = np.ones(len(hs))
+    for k in range(len(hs)):
+        for m in range(len(hs)):
+            if m != k:
+                w[k] *= hs[m] / (hs[m] - hs[k])
+    return w
+
+
+def step_sweep(t_min, t_max, beta, steps, model, tol=1e-10, max_iter=200,
+               use_graph=True):
+    """Solve the contour t in [t_min, t_max], beta with dt = dtau = h for every h
+    in steps (the coarsest first; each a whole multiple of the finest) in one
+    fk_batch, to delta < tol.  Returns the coarse times, per-step j, n, m0 on
+    that grid, their extrapolation to h = 0, and the iteration counts."""
+    steps = [float(h) for h in steps]
+    h0 = max(steps)
+    inst = [dict(t_min=t_min, t_max=t_max, dt=h, dtau=h, beta=beta, **model) for h in steps]
+    per = {}
+    with fkdmft.Batch(inst) as b:
+        r = b.iterate(max_iter, tol=tol, use_graph=use_graph)
+        if not np.all(r["deltas"] < tol):
+            raise RuntimeError(f"not converged: deltas {r['deltas']}")
+        t_coarse = None
+        for i, h in enumerate(steps):
+            c = b.instance(i)
+            t, j, n = c.get_current()
+            m0 = c.get_zeroth_moment()
+            s = int(round(h0 / h))
+            if abs(s * h - h0) > 1e-9 * h0:
+                raise ValueError("steps must divide the coarsest step")
+            if h == h0:
+                t_coarse = t
+            nc = int(round((t_max - t_min) / h0))
+            per[h] = dict(j=j[::s][:nc], n=n[::s][:nc], m0=m0[::s][:nc])
+    w = lagrange_weights(steps)
+    ext = {q: sum(w[k] * per[h][q] for k, h in enumerate(steps)) for q in ("j", "n", "m0")}
+    return dict(t=t_coarse, per_step=per, extrapolated=ext, weights=w,
+                iters=[int(v) for v in r["iters"]])

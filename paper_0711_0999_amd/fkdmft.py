@@ -84,6 +84,7 @@ SIGNATURES = {
     "fk_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_low_iterations": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "fk_get_zeroth_moment": (ctypes.c_int, [_vp, _dp]),
     "fk_get_point_green": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "fk_set_kernel_clock": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fk_kernel_clock": (ctypes.c_int, [_vp, _dp]),
@@ -295,6 +296,11 @@ class Context:
         self._check(self._lib.fk_get_current(self._h, _dptr(t), _dptr(j), _dptr(n)),
                     "fk_get_current")
         return t, j, n
+
+    def get_zeroth_moment(self):
+        m = np.zeros(2 * self.n_t)
+        self._check(self._lib.fk_get_zeroth_moment(self._h, _dptr(m)), "fk_get_zeroth_moment")
+        return m.view(np.complex128)
 
     def impurity_update(self):
         d = ctypes.c_double()

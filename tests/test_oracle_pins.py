@@ -647,3 +647,20 @@ def test_averaged_quadrature_counts_and_moments():
     e2, b2, r2 = quadrature.product_grid(7, 8)
     m = lambda ee, rr: np.sum(rr * ee ** 12)
     assert abs(np.sum(r * e ** 12) - 0.5 * (m(e1, r1) + m(e2, r2))) < 1e-9
+
+
+def test_neville_extrapolation_is_exact_for_polynomials():
+    """Extrapolation to dt = 0 through k points reproduces any polynomial of
+    degree < k exactly (the Lagrange extrapolation of the paper's accuracy
+    discussion), and a linear rule from two points cancels the O(dt) term."""
+    from oracle import extrapolate
+    hs = [0.2, 0.1, 0.05]
+    for coeffs in ([3.0], [1.0, -2.0], [0.5, 4.0, -7.0]):
+        f = [sum(c * h ** p for p, c in enumerate(coeffs)) for h in hs]
+        assert abs(extrapolate.to_zero(hs, f) - coeffs[0]) < 1e-12
+    # vector values, elementwise
+    f = [np.array([1 + h, 2 - 3 * h]) for h in hs[:2]]
+    assert np.allclose(extrapolate.to_zero(hs[:2], f), [1, 2], atol=1e-13)
+    # a cubic through three points is not reproduced (degree too high)
+    f = [h ** 3 for h in hs]
+    assert abs(extrapolate.to_zero(hs, f)) > 1e-4
