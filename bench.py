@@ -73,13 +73,53 @@ def cpu_baseline(w, n_sample=48):
                       "scaled to all points"}
 
 
+def sweep_bench(args):
+    """C4: one multi-instance sweep (every instance's lattice step in shared
+    batched launches of uneven matrices, plus all impurity updates), recorded
+    once in a hipGraph and replayed; seconds per sweep and the achieved rate of
+    the inversions (8 N_c^3 flops per point, summed over the instances)."""
+    import torch
+
+    from paper_0711_0999_amd import configs, fkdmft
+
+    inst = configs.c4_instances(count=args.instances)
+    flops = sum(8.0 * (round((2 * d["t_max"] + 30) / d["dt"])) ** 3 * d["n_eps"] * d["n_ebar"]
+                for d in inst)
+    with fkdmft.Batch(inst) as b:
+        t0 = time.perf_counter()
+        b.iterate(max(args.warmup, 1), tol=0.0, use_graph=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        log(f"bench: warm-up sweep(s) incl. plan and graph recording {t1 - t0:.1f} s")
+        b.iterate(args.steps, tol=0.0, use_graph=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tm = b.timings()
+    sec = (t2 - t1) / args.steps
+    achieved = flops / sec / 1e12
+    n_cs = sorted({int(round((2 * d["t_max"] + 30) / d["dt"])) for d in inst})
+    print(json.dumps({
+        "metric": "sec per multi-instance sweep (C4)", "value": sec, "unit": "s/sweep",
+        "n_gpus": 1, "steps": args.steps, "warmup": max(args.warmup, 1),
+        "ms_per_step": sec * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": f"C4: {len(inst)} instances, N_c in {n_cs}, "
+                               "n x n points, n = 35..55", "parallelism": "1 GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": None, "kernel": "whole sweep (inversions, 8 N_c^3 per point)"},
+        "graph": {"captures": tm["captures"], "capture_ms": tm["capture_ms"]},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--U", type=float, default=1.0)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--converge", action="store_true")
     ap.add_argument("--batch", type=int, default=0)
@@ -101,6 +141,9 @@ def main():
     from paper_0711_0999_amd import configs, fkdmft
 
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        sweep_bench(args)
+        return
     stream = torch.cuda.current_stream()
     w = configs.c2(args.U) if args.workload == "c2" else configs.C1
     ctx = fkdmft.Context(stream=stream, **w.kwargs())

@@ -58,3 +58,23 @@ def c3(E):
 
 
 C3_E = (0.5, 1.0, 2.0, 4.0)
+
+
+def c4_instances(seed=0, count=32):
+    """C4: a batched uneven sweep of `count` (U, E) instances, U ~ U[0.25, 2.5],
+    E ~ U[0.5, 4], (dt, t_max) uniform on {0.1, 1/15, 0.05} x {10, 20, 30},
+    t_min = -10, dtau = dt, beta = 10 (so N_c = (2 t_max + 30)/dt in
+    {500 .. 1800}), Gauss-Hermite order n = 35 + round(20 (N_c - 500)/1300)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        u = float(rng.uniform(0.25, 2.5))
+        e = float(rng.uniform(0.5, 4.0))
+        dt = (0.1, 1.0 / 15.0, 0.05)[int(rng.integers(3))]
+        t_max = (10.0, 20.0, 30.0)[int(rng.integers(3))]
+        n_c = int(round((2 * t_max + 30) / dt))
+        n = 35 + int(round(20 * (n_c - 500) / 1300))
+        out.append(dict(t_min=-10.0, t_max=t_max, dt=dt, dtau=dt, beta=10.0, U=u, E=e,
+                        n_eps=n, n_ebar=n))
+    return out
