@@ -45,7 +45,7 @@ enum {
   FK_ESTATE = -7       /* call order violated (e.g. current before a step)      */
 };
 
-/* Arithmetic of the lattice step (north of the FP64 reduction). */
+/* Arithmetic of the lattice step up to its FP64 reduction. */
 typedef enum {
   FK_FP64 = 0,   /* complex128 Gauss-Jordan inversion of every point matrix      */
   FK_MIXED = 1   /* complex64 inversion + FP64 iterative refinement (see below)  */
