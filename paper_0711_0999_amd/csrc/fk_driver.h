@@ -301,6 +301,11 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
     if ((e = gje_gather<T>(b.x, b.bbuf, b.piv, b.descs, nmat, S, st)) != hipSuccess)
       return e;
     ++nl;
+    if (S > 0) {
+      if ((e = gje_fix<T>(b.x, b.bbuf, b.piv, b.descs, nmat, S, st)) != hipSuccess)
+        return e;
+      ++nl;
+    }
     if (next) {
       const int nN = b.uniform ? nmat * b.cntN[S] : b.totN[S];
       if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offN[S],

@@ -5,15 +5,19 @@
 //
 // Outer step S handles the block of kNBO = 128 columns starting at J0 = S*kNBO:
 //   panel   (one 512-thread workgroup per matrix) eliminates the block's two
-//           64-column inner panels in turn.  For each column the pivot is the
-//           largest |re|+|im| among the rows not yet pivoted; kIB columns are
-//           eliminated in registers at a time, the rest of the inner panel is
-//           updated in coalesced passes, and the other inner panel receives
-//           the rank-64 transform on the matrix cores.  Afterwards the block
-//           holds the transformed identity columns M = E[:, P] of all
-//           elementary Gauss-Jordan transforms of the step.
-//   gather  copies the pivot rows P of the step (their values before the
-//           step) into a side buffer B.
+//           64-column inner panels in turn on the n - J0 rows not pivoted in
+//           earlier blocks.  For each column the pivot is the largest
+//           |re|+|im| among the rows not yet pivoted; kIB columns are
+//           eliminated in registers at a time, the rest of the inner panel
+//           receives rank-kIB updates row by row, and the other inner panel
+//           the rank-64 transform on the matrix cores.
+//   gather  copies the pivot rows of the step into a side buffer B (their
+//           values before the step outside the block, the block's inverse
+//           pivot submatrix inside it).
+//   fix     the block's columns of the J0 rows pivoted earlier, from that
+//           inverse (one small product per row tile).  The block now holds
+//           the transformed identity columns M = E[:, P] of all elementary
+//           Gauss-Jordan transforms of the step.
 //   update  every other column tile: C <- mask_P(C) + M B (K = 128), a batched
 //           complex GEMM on the matrix cores (four real products per complex
 //           one), double-buffered K chunks in LDS, two workgroups per CU.
@@ -80,6 +84,7 @@ constexpr int kRB = kTile / (16 * (kPW / 4));   // 16-row blocks per wave
 static_assert(kPW % 4 == 0 && kRB >= 1, "panel waves");
 template <typename T>
 __device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, int n,
+                             const int* __restrict__ rows, int m,
                              const int* __restrict__ piv,
                              const int* __restrict__ rowcol, int p, int q,
                              unsigned char* smem) {
@@ -116,31 +121,32 @@ __device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, in
   const int wr = wave >> 2, wc = wave & 3;
   const int li = lane & 15, lk = lane >> 4;
   const int col = 16 * wc + li;
-  for (int r0 = 0; r0 < n; r0 += kTile) {
+  for (int r0 = 0; r0 < m; r0 += kTile) {
     __syncthreads();
     cplx<T> mv[kL];
 #pragma unroll
     for (int t = 0; t < kL; ++t) {
       const int e = tid + t * kPanelThreads;
       const int i = e / kNB, l = e % kNB;
-      mv[t] = x[(size_t)min(r0 + i, n - 1) * ld + j0 + min(l, w - 1)];
+      mv[t] = x[(size_t)rows[min(r0 + i, m - 1)] * ld + j0 + min(l, w - 1)];
     }
-    int rcv[kRB][4];
+    int rid[kRB][4], rcv[kRB][4];
     cplx<T> cv[kRB][4];
 #pragma unroll
     for (int ii = 0; ii < kRB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
-        rcv[ii][v] = rowcol[min(row, n - 1)];
-        cv[ii][v] = x[(size_t)min(row, n - 1) * ld + c0 + min(col, cw - 1)];
+        const int e = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        rid[ii][v] = rows[min(e, m - 1)];
+        rcv[ii][v] = rowcol[rid[ii][v]];
+        cv[ii][v] = x[(size_t)rid[ii][v] * ld + c0 + min(col, cw - 1)];
       }
 #pragma unroll
     for (int t = 0; t < kL; ++t) {
       const int e = tid + t * kPanelThreads;
       const int i = e / kNB, l = e % kNB;
       cplx<T> v = mv[t];
-      if (!(r0 + i < n && l < w)) v.re = v.im = T(0);
+      if (!(r0 + i < m && l < w)) v.re = v.im = T(0);
       Ms[i * kPitch + l] = v;
     }
     v4 cr[kRB], ci[kRB];
@@ -148,8 +154,8 @@ __device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, in
     for (int ii = 0; ii < kRB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
-        const bool keep = row < n && col < cw &&
+        const int e = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        const bool keep = e < m && col < cw &&
                           !(rcv[ii][v] >= j0 && rcv[ii][v] < j0 + w);
         cr[ii][v] = keep ? cv[ii][v].re : T(0);
         ci[ii][v] = keep ? cv[ii][v].im : T(0);
@@ -171,12 +177,12 @@ __device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, in
     for (int ii = 0; ii < kRB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
-        if (row < n && col < cw) {
+        const int e = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        if (e < m && col < cw) {
           cplx<T> c;
           c.re = cr[ii][v];
           c.im = ci[ii][v];
-          x[(size_t)row * ld + c0 + col] = c;
+          x[(size_t)rid[ii][v] * ld + c0 + col] = c;
         }
       }
   }
@@ -188,9 +194,13 @@ template <typename T> struct GroupBatch { static constexpr int value = 4; };
 template <> struct GroupBatch<float> { static constexpr int value = 7; };
 
 // ---------------------------------------------------- panel: factorization
-// Eliminate the columns of inner panel q (all rows) with partial pivoting.
+// Eliminate the columns of inner panel q on the listed rows rows[0, m) (the
+// rows not pivoted before this outer block) with partial pivoting.  Thread tid
+// owns list entries tid + i * kPanelThreads; the list is in ascending row
+// order, so a tie of pivot keys goes to the lowest row index.
 template <typename T>
 __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
+                             const int* __restrict__ rows, int m,
                              int* __restrict__ piv, int* __restrict__ rowcol,
                              int q, int* __restrict__ status,
                              unsigned char* smem) {
@@ -205,10 +215,12 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
   constexpr int kGB = GroupBatch<T>::value;
 
   bool pvd[kRPT];
+  int rr[kRPT];
 #pragma unroll
   for (int i = 0; i < kRPT; ++i) {
-    const int r = tid + i * kPanelThreads;
-    pvd[i] = (r < n) ? (rowcol[min(r, n - 1)] >= 0) : true;
+    const int e = tid + i * kPanelThreads;
+    rr[i] = rows[min(e, m - 1)];
+    pvd[i] = (e < m) ? (rowcol[rr[i]] >= 0) : true;
   }
   const int ngroups = (cw + kIB - 1) / kIB;
 
@@ -217,33 +229,33 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
     cplx<T> v[kRPT][kIB];
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
-      const int r = min(tid + i * kPanelThreads, n - 1);
 #pragma unroll
       for (int l = 0; l < kIB; ++l)
-        v[i][l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
+        v[i][l] = x[(size_t)rr[i] * ld + c0 + b0 + min(l, iw - 1)];
     }
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
-      const int r = tid + i * kPanelThreads;
+      const int e = tid + i * kPanelThreads;
 #pragma unroll
       for (int l = 0; l < kIB; ++l)
-        if (!(r < n && l < iw)) v[i][l].re = v[i][l].im = T(0);
+        if (!(e < m && l < iw)) v[i][l].re = v[i][l].im = T(0);
     }
 #pragma unroll
     for (int l = 0; l < kIB; ++l) {
       if (l >= iw) break;
-      // ---- pivot search: largest |re|+|im| among unpivoted rows
+      // ---- pivot search: largest |re|+|im| among unpivoted rows (bidx is
+      // a list index)
       T best = T(-1);
       int bidx = INT_MAX;
 #pragma unroll
       for (int i = 0; i < kRPT; ++i) {
-        const int r = tid + i * kPanelThreads;
-        if (r < n && !pvd[i]) {
+        const int e = tid + i * kPanelThreads;
+        if (e < m && !pvd[i]) {
           T a = fabs(v[i][l].re) + fabs(v[i][l].im);
           if (!(a <= inf_key)) a = inf_key;  // NaN / Inf win and get flagged
-          if (a > best || (a == best && r < bidx)) {
+          if (a > best || (a == best && e < bidx)) {
             best = a;
-            bidx = r;
+            bidx = e;
           }
         }
       }
@@ -272,12 +284,15 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
           bidx = oi;
         }
       }
-      const int p = bidx;  // a valid unpivoted row: fewer than n pivots so far
+      // a valid unpivoted entry: the list holds more rows than this block
+      // has columns
+      const int pe = bidx;
+      const int p = rows[min(pe, m - 1)];
       const int col = c0 + b0 + l;
       if (tid == 0 && (best == T(0) || best == inf_key))
         atomicCAS(status, 0, best == T(0) ? (1 + col) : -(1 + col));
-      if ((p % kPanelThreads) == tid) {
-        const int i = p / kPanelThreads;
+      if ((pe % kPanelThreads) == tid) {
+        const int i = pe / kPanelThreads;
 #pragma unroll
         for (int ii = 0; ii < kRPT; ++ii)
           if (ii == i) {
@@ -302,8 +317,8 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       ps[l] = inv;
 #pragma unroll
       for (int i = 0; i < kRPT; ++i) {
-        const int r = tid + i * kPanelThreads;
-        if (r == p) {
+        const int e = tid + i * kPanelThreads;
+        if (e == pe) {
 #pragma unroll
           for (int l2 = 0; l2 < kIB; ++l2) v[i][l2] = ps[l2];
         } else {
@@ -324,11 +339,11 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
     // ---- write the eliminated block back; old pivot rows of the other columns
 #pragma unroll
     for (int i = 0; i < kRPT; ++i) {
-      const int r = tid + i * kPanelThreads;
-      if (r < n) {
+      const int e = tid + i * kPanelThreads;
+      if (e < m) {
 #pragma unroll
         for (int l = 0; l < kIB; ++l)
-          if (l < iw) x[(size_t)r * ld + c0 + b0 + l] = v[i][l];
+          if (l < iw) x[(size_t)rr[i] * ld + c0 + b0 + l] = v[i][l];
       }
     }
     for (int e = tid; e < kIB * kNB; e += kPanelThreads) {
@@ -349,8 +364,9 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
     for (int l = 0; l < kIB; ++l) pv0[l] = (l < iw) ? pvt[l] : -1;
 #pragma unroll 1
     for (int i = 0; i < kRPT; ++i) {
-      const int r = tid + i * kPanelThreads;
-      if (r >= n) continue;
+      const int e = tid + i * kPanelThreads;
+      if (e >= m) break;
+      const int r = rows[e];
       bool isp = false;
 #pragma unroll
       for (int l = 0; l < kIB; ++l) isp |= (pv0[l] == r);
@@ -395,6 +411,23 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
   }
 }
 
+// LDS of the panel kernel: the larger of the two phases' buffers, then the
+// list of the rows the block works on.
+template <typename T> __host__ __device__ constexpr size_t panel_body_bytes() {
+  return ((sizeof(cplx<T>) * (size_t)(kNB + kTile) * kPitch >
+                   sizeof(cplx<T>) * (kIB * kNB + kIB) + kPW * sizeof(T) +
+                       kPW * sizeof(int) + kIB * sizeof(int)
+               ? sizeof(cplx<T>) * (size_t)(kNB + kTile) * kPitch
+               : sizeof(cplx<T>) * (kIB * kNB + kIB) + kPW * sizeof(T) +
+                     kPW * sizeof(int) + kIB * sizeof(int)) + 15) / 16 * 16;
+}
+template <typename T> static size_t panel_lds_bytes() {
+  return panel_body_bytes<T>() + sizeof(int) * (size_t)kMaxN;
+}
+
+// Outer block S of one matrix.  Rows pivoted in earlier blocks take no part:
+// their columns of this block follow from the block's pivot rows afterwards
+// (k_fix), so the panel reads and writes only the n - S kNBO remaining rows.
 template <typename T>
 __global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
     cplx<T>* __restrict__ xbuf, int* __restrict__ pivbuf,
@@ -408,15 +441,45 @@ __global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
   int* piv = pivbuf + d.ioff;
   int* rowcol = rowcolbuf + d.ioff;
   int* st = status + d.status_idx;
+
+  // list the unpivoted rows in ascending order (wave ballots, then offsets)
+  int* rows = reinterpret_cast<int*>(smem + panel_body_bytes<T>());
+  int* cnt = reinterpret_cast<int*>(smem);   // [kRPT][kPW], before the panel
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  unsigned long long bal[kRPT];
+#pragma unroll
+  for (int i = 0; i < kRPT; ++i) {
+    const int r = tid + i * kPanelThreads;
+    bal[i] = __ballot(r < n && rowcol[min(r, n - 1)] < 0);
+    if (lane == 0) cnt[i * kPW + wave] = (int)__popcll(bal[i]);
+  }
+  __syncthreads();
+  int m = 0;   // n - S kNBO unless earlier blocks failed to pivot
+  int pos[kRPT];
+#pragma unroll
+  for (int i = 0; i < kRPT; ++i) {
+    int before = 0;
+#pragma unroll
+    for (int wv = 0; wv < kPW; ++wv) before += (wv < wave) ? cnt[i * kPW + wv] : 0;
+    pos[i] = m + before + (int)__popcll(bal[i] & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int wv = 0; wv < kPW; ++wv) m += cnt[i * kPW + wv];
+  }
+#pragma unroll
+  for (int i = 0; i < kRPT; ++i)
+    if ((bal[i] >> lane) & 1ull) rows[pos[i]] = tid + i * kPanelThreads;
+  __syncthreads();
+  if (m == 0) return;   // the same for every thread
+
   const int p0 = 2 * S, p1 = 2 * S + 1;
-  factor_panel<T>(x, d.ld, n, piv, rowcol, p0, st, smem);
+  factor_panel<T>(x, d.ld, n, rows, m, piv, rowcol, p0, st, smem);
   if (p1 * kNB < n) {
     __syncthreads();
-    inner_update<T>(x, d.ld, n, piv, rowcol, p0, p1, smem);
+    inner_update<T>(x, d.ld, n, rows, m, piv, rowcol, p0, p1, smem);
     __syncthreads();
-    factor_panel<T>(x, d.ld, n, piv, rowcol, p1, st, smem);
+    factor_panel<T>(x, d.ld, n, rows, m, piv, rowcol, p1, st, smem);
     __syncthreads();
-    inner_update<T>(x, d.ld, n, piv, rowcol, p1, p0, smem);
+    inner_update<T>(x, d.ld, n, rows, m, piv, rowcol, p1, p0, smem);
   }
 }
 
@@ -434,6 +497,145 @@ __global__ void k_gather(const cplx<T>* __restrict__ xbuf,
   const cplx<T>* src = xbuf + d.xoff + (size_t)p * d.ld;
   cplx<T>* dst = bbuf + d.boff + (size_t)l * d.ld;
   for (int c = threadIdx.x; c < d.n; c += blockDim.x) dst[c] = src[c];
+}
+
+// ----------------------------------------------------------------- fix-up
+// Rows pivoted in earlier outer blocks skip the panel.  For such a row r the
+// block's Gauss-Jordan steps amount to X[r, P] <- -X0[r, P] Minv, with X0 the
+// row's values before the block and Minv = X[R, P] the block's pivot rows R in
+// pivot order after the panel (the inverse of X0[R, P]), which the gather has
+// copied into B.  Those rows are piv[0, J0) in pivot order; one 512-thread
+// workgroup takes 64 of them and all of the block's columns, reading its
+// rows' X0 before writing, so the product is formed in place.  Eight waves
+// as 2 x 4 blocks of 32 x 32, K in chunks of kKC double-buffered in LDS.
+template <typename T>
+__global__ __launch_bounds__(512, 1) void k_fix(
+    cplx<T>* __restrict__ xbuf, const cplx<T>* __restrict__ bbuf,
+    const int* __restrict__ pivbuf, const MatDesc* __restrict__ descs, int S) {
+  typedef typename Mfma<T>::v4 v4;
+  constexpr int TR = 64, TC = kNBO, NT = 512;
+  constexpr int AP = kKC + 1, BP = TC + 1;
+  __shared__ cplx<T> As[2][TR * AP];
+  __shared__ cplx<T> Bsh[2][kKC * BP];
+  constexpr int kLA = TR * kKC / NT;
+  constexpr int kLB = kKC * TC / NT;
+  static_assert(kLA * NT == TR * kKC && kLB * NT == kKC * TC, "fix tile");
+
+  const MatDesc d = descs[blockIdx.y];
+  const int n = d.n, ld = d.ld;
+  const int J0 = S * kNBO, i0 = blockIdx.x * TR;
+  if (J0 >= n || i0 + TR > J0) return;   // J0 is a multiple of TR
+  const int wO = min(kNBO, n - J0);
+  const int nch = (wO + kKC - 1) / kKC;
+  cplx<T>* xm = xbuf + d.xoff;
+  const cplx<T>* bm = bbuf + d.boff;
+  const int* piv = pivbuf + d.ioff;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int li = lane & 15, lk = lane >> 4;
+
+  int ra[kLA];
+#pragma unroll
+  for (int t = 0; t < kLA; ++t) ra[t] = piv[i0 + (tid + t * NT) / kKC];
+  cplx<T> pa[kLA], pb[kLB];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int t = 0; t < kLA; ++t) {
+      const int k = (tid + t * NT) % kKC;
+      pa[t] = xm[(size_t)ra[t] * ld + J0 + min(kb + k, wO - 1)];
+    }
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+      const int e = tid + t * NT;
+      const int k = e / TC, c = e % TC;
+      pb[t] = bm[(size_t)min(kb + k, wO - 1) * ld + J0 + min(c, wO - 1)];
+    }
+  };
+  auto stash = [&](int kb, int buf) {
+#pragma unroll
+    for (int t = 0; t < kLA; ++t) {
+      const int e = tid + t * NT;
+      const int i = e / kKC, k = e % kKC;
+      cplx<T> v = pa[t];
+      if (!(kb + k < wO)) v.re = v.im = T(0);
+      As[buf][i * AP + k] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+      const int e = tid + t * NT;
+      const int k = e / TC, c = e % TC;
+      cplx<T> v = pb[t];
+      if (!(kb + k < wO && c < wO)) v.re = v.im = T(0);
+      Bsh[buf][k * BP + c] = v;
+    }
+  };
+  v4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cr[ii][jj][v] = T(0);
+        ci[ii][jj][v] = T(0);
+      }
+  load(0);
+  stash(0, 0);
+  __syncthreads();
+  for (int kc = 0; kc < nch; ++kc) {
+    const int buf = kc & 1;
+    const bool more = kc + 1 < nch;
+    if (more) load((kc + 1) * kKC);
+    const cplx<T>* as = As[buf];
+    const cplx<T>* bs = Bsh[buf];
+#pragma unroll
+    for (int k = 0; k < kKC; k += 4) {
+      T ar[2], ai[2], an[2], br[2], bi[2];
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii) {
+        const cplx<T> a = as[(32 * wr + 16 * ii + li) * AP + k + lk];
+        ar[ii] = a.re;
+        ai[ii] = a.im;
+        an[ii] = -a.im;
+      }
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const cplx<T> b = bs[(k + lk) * BP + 32 * wc + 16 * jj + li];
+        br[jj] = b.re;
+        bi[jj] = b.im;
+      }
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          cr[ii][jj] = Mfma<T>::run(ar[ii], br[jj], cr[ii][jj]);
+          ci[ii][jj] = Mfma<T>::run(ar[ii], bi[jj], ci[ii][jj]);
+          cr[ii][jj] = Mfma<T>::run(an[ii], bi[jj], cr[ii][jj]);
+          ci[ii][jj] = Mfma<T>::run(ai[ii], br[jj], ci[ii][jj]);
+        }
+    }
+    if (more) stash((kc + 1) * kKC, buf ^ 1);
+    __syncthreads();
+  }
+  // every global read of the rows is done (last barrier): write in place
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = piv[i0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v)];
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj) {
+        const int col = 32 * wc + 16 * jj + li;
+        if (col < wO) {
+          cplx<T> c;
+          c.re = -cr[ii][jj][v];
+          c.im = -ci[ii][jj][v];
+          xm[(size_t)r * ld + J0 + col] = c;
+        }
+      }
+    }
 }
 
 // ------------------------------------------------------------------ update
@@ -631,13 +833,6 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
 }
 
 // --------------------------------------------------------------- launchers
-template <typename T> static size_t panel_lds_bytes() {
-  const size_t upd = sizeof(cplx<T>) * (size_t)(kNB + kTile) * kPitch;
-  const size_t fac = sizeof(cplx<T>) * (kIB * kNB + kIB) + kPW * sizeof(T) +
-                     kPW * sizeof(int) + kIB * sizeof(int);
-  return upd > fac ? upd : fac;
-}
-
 template <typename T>
 hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
                      int nmat, int S, int* status, hipStream_t st) {
@@ -666,6 +861,15 @@ hipError_t gje_gather(const cplx<T>* x, cplx<T>* bbuf, const int* piv,
 }
 
 template <typename T>
+hipError_t gje_fix(cplx<T>* x, const cplx<T>* bbuf, const int* piv,
+                   const MatDesc* d, int nmat, int S, hipStream_t st) {
+  if (nmat <= 0 || S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fix<T>, dim3(S * kNBO / 64, nmat), dim3(512), 0, st, x,
+                     bbuf, piv, d, S);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
                       const MatDesc* d, const TileItem* items, int nitems,
                       int S, int variant, hipStream_t st) {
@@ -687,6 +891,8 @@ hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
                                    int, int*, hipStream_t);                   \
   template hipError_t gje_gather<T>(const cplx<T>*, cplx<T>*, const int*,     \
                                     const MatDesc*, int, int, hipStream_t);   \
+  template hipError_t gje_fix<T>(cplx<T>*, const cplx<T>*, const int*,       \
+                                 const MatDesc*, int, int, hipStream_t);      \
   template hipError_t gje_update<T>(cplx<T>*, const cplx<T>*, const int*,     \
                                     const MatDesc*, const TileItem*, int, int, \
                                     int, hipStream_t);

@@ -45,6 +45,7 @@ constexpr int kMaxN = 2048;      // largest matrix the inversion supports
 // Outer step S of the blocked in-place Gauss-Jordan inversion, pieces:
 //   panel   one workgroup per matrix factors the outer block [S*kNBO, +kNBO)
 //   gather  copies the old pivot rows of outer step S into the side buffer
+//   fix     the block's columns of the rows pivoted before step S
 //   update  C <- mask(C) + M B on the listed tiles (K = outer block width)
 template <typename T>
 hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
@@ -52,6 +53,9 @@ hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
 template <typename T>
 hipError_t gje_gather(const cplx<T>* x, cplx<T>* bbuf, const int* piv,
                       const MatDesc* d, int nmat, int S, hipStream_t st);
+template <typename T>
+hipError_t gje_fix(cplx<T>* x, const cplx<T>* bbuf, const int* piv,
+                   const MatDesc* d, int nmat, int S, hipStream_t st);
 // variant 0: 64 x 64 tiles (256 threads); 1: 128 x 64 tiles (512 threads).
 // TileItem.tr counts tiles of tile_rows(variant) rows.
 template <typename T>

@@ -77,3 +77,55 @@ def test_create_rejects_averaged_rule_beyond_150_points(lib):
     with pytest.raises(lib.FkError) as e:
         lib.Context(-5, 5, 0.2, 0.2, 10, 0.5, 1.0, n_eps=150, n_ebar=10, gh_average=True)
     assert e.value.status == lib.FK_EINVAL
+
+
+def _gauss_jordan_block(x, cols, candidates):
+    """In-place Gauss-Jordan elimination of the columns `cols` of x with partial
+    pivoting among `candidates`; returns the pivot rows in pivot order."""
+    piv = []
+    for c in cols:
+        free = [r for r in candidates if r not in piv]
+        p = max(free, key=lambda r: abs(x[r, c].real) + abs(x[r, c].imag))
+        piv.append(p)
+        inv = 1.0 / x[p, c]
+        ps = x[p, :] * inv
+        ps[c] = inv
+        for r in range(x.shape[0]):
+            if r != p:
+                m = x[r, c]
+                x[r, :] -= m * ps
+                x[r, c] = -m * inv
+        x[p, :] = ps
+    return piv
+
+
+def test_deferred_rows_block_identity():
+    """The identity the panel relies on when it leaves out the rows pivoted in
+    earlier blocks: after eliminating a block of columns P with pivot rows R,
+    every other row r holds X[r, P] = -X0[r, P] X[R, P], and X[R, P] (rows in
+    pivot order) is the inverse of X0[R, P].  Checked on a random complex
+    matrix, with the blocked inverse assembled this way equal to numpy's."""
+    rng = np.random.default_rng(11)
+    n, w = 24, 8
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    x = a.copy()
+    done = []
+    for j0 in range(0, n, w):
+        cols = list(range(j0, j0 + w))
+        x0 = x.copy()
+        cand = [r for r in range(n) if r not in done]
+        full = x.copy()
+        piv = _gauss_jordan_block(full, cols, cand)
+        minv = full[np.ix_(piv, cols)]
+        np.testing.assert_allclose(minv, np.linalg.inv(x0[np.ix_(piv, cols)]),
+                                   rtol=1e-12, atol=1e-12)
+        for r in done:
+            np.testing.assert_allclose(full[r, cols], -x0[r, cols] @ minv,
+                                       rtol=1e-12, atol=1e-12)
+        x = full
+        done += piv
+    # inv(A)[a][b] = X[piv[a]][rowcol[b]]
+    rowcol = np.empty(n, int)
+    rowcol[done] = np.arange(n)
+    inv = x[np.ix_(done, rowcol)]
+    np.testing.assert_allclose(inv, np.linalg.inv(a), rtol=1e-10, atol=1e-12)
