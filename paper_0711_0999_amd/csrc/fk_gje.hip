@@ -75,86 +75,89 @@ constexpr int kPitch = kNB + 1;                  // padded LDS row (elements)
 static_assert(kMaxN % kPanelThreads == 0, "kMaxN");
 static_assert(kNBO == 2 * kNB && kTile == kNB, "block sizes");
 
-// ------------------------------------------------------ panel: inner update
-// C <- mask(C) + M B on the 64-column stripe q of one matrix, with M the
-// columns of inner panel p (already eliminated) and B the old values of p's
-// pivot rows in stripe q (read before any write: this workgroup owns q).
-// The kPW waves form (kPW/4) x 4 blocks of (16 kRB) x 16 over each 64 x 64 tile.
-constexpr int kRB = kTile / (16 * (kPW / 4));   // 16-row blocks per wave
-static_assert(kPW % 4 == 0 && kRB >= 1, "panel waves");
-template <typename T>
-__device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, int n,
+// ------------------------------------------------------ panel: cross update
+// C <- mask(C) + M B on the columns [c0, c0 + cw) of one matrix's listed rows,
+// with M the already eliminated columns [j0, j0 + w) and B the values of their
+// pivot rows in [c0, c0 + cw) (read before any write: this workgroup owns the
+// matrix).  KW >= w and CW >= cw are the compile-time widths (32 or 64).  The
+// kPW waves form (kPW / (CW/16)) x (CW/16) blocks of (16 RB) x 16 over each
+// 64-row tile.
+template <typename T, int KW, int CW>
+__device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
                              const int* __restrict__ rows, int m,
                              const int* __restrict__ piv,
-                             const int* __restrict__ rowcol, int p, int q,
-                             unsigned char* smem) {
+                             const int* __restrict__ rowcol, int j0, int w,
+                             int c0, int cw, unsigned char* smem) {
   typedef typename Mfma<T>::v4 v4;
-  cplx<T>* Bs = reinterpret_cast<cplx<T>*>(smem);   // [kNB][kPitch]
-  cplx<T>* Ms = Bs + kNB * kPitch;                   // [kTile][kPitch]
+  constexpr int NCB = CW / 16, NRW = kPW / NCB, RB = kTile / (16 * NRW);
+  static_assert(NCB * NRW == kPW && RB >= 1 && 16 * RB * NRW == kTile, "waves");
+  constexpr int KP = KW + 1, CP = CW + 1;
+  cplx<T>* Bs = reinterpret_cast<cplx<T>*>(smem);   // [KW][CP]
+  cplx<T>* Ms = Bs + KW * CP;                        // [kTile][KP]
+  constexpr int kLB = KW * CW / kPanelThreads;      // B elements per thread
+  constexpr int kLM = kTile * KW / kPanelThreads;   // M elements per thread
+  static_assert(kLB * kPanelThreads == KW * CW && kLM * kPanelThreads == kTile * KW, "loads");
   const int tid = threadIdx.x;
-  const int j0 = p * kNB, w = min(kNB, n - j0);
-  const int c0 = q * kNB, cw = min(kNB, n - c0);
-  constexpr int kL = kNB * kNB / kPanelThreads;     // elements per thread
   {
-    int pr[kL];
-    cplx<T> bv[kL];
+    int pr[kLB];
+    cplx<T> bv[kLB];
 #pragma unroll
-    for (int t = 0; t < kL; ++t) {
-      const int l = (tid + t * kPanelThreads) / kNB;
+    for (int t = 0; t < kLB; ++t) {
+      const int l = (tid + t * kPanelThreads) / CW;
       pr[t] = piv[j0 + min(l, w - 1)];
     }
 #pragma unroll
-    for (int t = 0; t < kL; ++t) {
-      const int c = (tid + t * kPanelThreads) % kNB;
+    for (int t = 0; t < kLB; ++t) {
+      const int c = (tid + t * kPanelThreads) % CW;
       bv[t] = x[(size_t)pr[t] * ld + c0 + min(c, cw - 1)];
     }
 #pragma unroll
-    for (int t = 0; t < kL; ++t) {
+    for (int t = 0; t < kLB; ++t) {
       const int e = tid + t * kPanelThreads;
-      const int l = e / kNB, c = e % kNB;
+      const int l = e / CW, c = e % CW;
       cplx<T> v = bv[t];
       if (!(l < w && c < cw)) v.re = v.im = T(0);
-      Bs[l * kPitch + c] = v;
+      Bs[l * CP + c] = v;
     }
   }
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 2, wc = wave & 3;
+  const int wr = wave / NCB, wc = wave % NCB;
   const int li = lane & 15, lk = lane >> 4;
   const int col = 16 * wc + li;
   for (int r0 = 0; r0 < m; r0 += kTile) {
     __syncthreads();
-    cplx<T> mv[kL];
+    cplx<T> mv[kLM];
 #pragma unroll
-    for (int t = 0; t < kL; ++t) {
+    for (int t = 0; t < kLM; ++t) {
       const int e = tid + t * kPanelThreads;
-      const int i = e / kNB, l = e % kNB;
+      const int i = e / KW, l = e % KW;
       mv[t] = x[(size_t)rows[min(r0 + i, m - 1)] * ld + j0 + min(l, w - 1)];
     }
-    int rid[kRB][4], rcv[kRB][4];
-    cplx<T> cv[kRB][4];
+    int rid[RB][4], rcv[RB][4];
+    cplx<T> cv[RB][4];
 #pragma unroll
-    for (int ii = 0; ii < kRB; ++ii)
+    for (int ii = 0; ii < RB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int e = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        const int e = r0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
         rid[ii][v] = rows[min(e, m - 1)];
         rcv[ii][v] = rowcol[rid[ii][v]];
         cv[ii][v] = x[(size_t)rid[ii][v] * ld + c0 + min(col, cw - 1)];
       }
 #pragma unroll
-    for (int t = 0; t < kL; ++t) {
+    for (int t = 0; t < kLM; ++t) {
       const int e = tid + t * kPanelThreads;
-      const int i = e / kNB, l = e % kNB;
+      const int i = e / KW, l = e % KW;
       cplx<T> v = mv[t];
       if (!(r0 + i < m && l < w)) v.re = v.im = T(0);
-      Ms[i * kPitch + l] = v;
+      Ms[i * KP + l] = v;
     }
-    v4 cr[kRB], ci[kRB];
+    v4 cr[RB], ci[RB];
 #pragma unroll
-    for (int ii = 0; ii < kRB; ++ii)
+    for (int ii = 0; ii < RB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int e = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        const int e = r0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
         const bool keep = e < m && col < cw &&
                           !(rcv[ii][v] >= j0 && rcv[ii][v] < j0 + w);
         cr[ii][v] = keep ? cv[ii][v].re : T(0);
@@ -162,11 +165,11 @@ __device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, in
       }
     __syncthreads();
 #pragma unroll 4
-    for (int k = 0; k < kNB; k += 4) {
-      const cplx<T> b = Bs[(k + lk) * kPitch + col];
+    for (int k = 0; k < KW; k += 4) {
+      const cplx<T> b = Bs[(k + lk) * CP + col];
 #pragma unroll
-      for (int ii = 0; ii < kRB; ++ii) {
-        const cplx<T> a = Ms[(16 * (kRB * wr + ii) + li) * kPitch + k + lk];
+      for (int ii = 0; ii < RB; ++ii) {
+        const cplx<T> a = Ms[(16 * (RB * wr + ii) + li) * KP + k + lk];
         cr[ii] = Mfma<T>::run(a.re, b.re, cr[ii]);
         ci[ii] = Mfma<T>::run(a.re, b.im, ci[ii]);
         cr[ii] = Mfma<T>::run(-a.im, b.im, cr[ii]);
@@ -174,10 +177,10 @@ __device__ __forceinline__ void inner_update(cplx<T>* __restrict__ x, int ld, in
       }
     }
 #pragma unroll
-    for (int ii = 0; ii < kRB; ++ii)
+    for (int ii = 0; ii < RB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int e = r0 + 16 * (kRB * wr + ii) + Mfma<T>::drow(lk, v);
+        const int e = r0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
         if (e < m && col < cw) {
           cplx<T> c;
           c.re = cr[ii][v];
@@ -194,23 +197,24 @@ template <typename T> struct GroupBatch { static constexpr int value = 4; };
 template <> struct GroupBatch<float> { static constexpr int value = 7; };
 
 // ---------------------------------------------------- panel: factorization
-// Eliminate the columns of inner panel q on the listed rows rows[0, m) (the
-// rows not pivoted before this outer block) with partial pivoting.  Thread tid
-// owns list entries tid + i * kPanelThreads; the list is in ascending row
-// order, so a tie of pivot keys goes to the lowest row index.
-template <typename T>
+// Eliminate the PW (32 or 64) columns starting at c0 on the listed rows
+// rows[0, m) (the rows not pivoted before this outer block) with partial
+// pivoting.  Thread tid owns list entries tid + i * kPanelThreads; the list is
+// in ascending row order, so a tie of pivot keys goes to the lowest row index.
+template <typename T, int PW>
 __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
                              const int* __restrict__ rows, int m,
                              int* __restrict__ piv, int* __restrict__ rowcol,
-                             int q, int* __restrict__ status,
+                             int c0, int* __restrict__ status,
                              unsigned char* smem) {
-  cplx<T>* Bo = reinterpret_cast<cplx<T>*>(smem);   // [kIB][kNB]
-  cplx<T>* prow = Bo + kIB * kNB;                    // [kIB]
+  static_assert(PW % kIB == 0 && PW <= kNB, "panel width");
+  cplx<T>* Bo = reinterpret_cast<cplx<T>*>(smem);   // [kIB][PW]
+  cplx<T>* prow = Bo + kIB * PW;                     // [kIB]
   T* redv = reinterpret_cast<T*>(prow + kIB);        // [kPW]
   int* redi = reinterpret_cast<int*>(redv + kPW);    // [kPW]
   int* pvt = redi + kPW;                             // [kIB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = q * kNB, cw = min(kNB, n - c0);
+  const int cw = min(PW, n - c0);
   const T inf_key = big_value<T>();
   constexpr int kGB = GroupBatch<T>::value;
 
@@ -346,8 +350,8 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
           if (l < iw) x[(size_t)rr[i] * ld + c0 + b0 + l] = v[i][l];
       }
     }
-    for (int e = tid; e < kIB * kNB; e += kPanelThreads) {
-      const int l = e / kNB, c = e % kNB;
+    for (int e = tid; e < kIB * PW; e += kPanelThreads) {
+      const int l = e / PW, c = e % PW;
       const bool ok = l < iw && c < cw && (c < b0 || c >= b0 + iw);
       cplx<T> t = x[(size_t)pvt[min(l, iw - 1)] * ld + c0 + min(c, cw - 1)];
       if (!ok) t.re = t.im = T(0);
@@ -377,7 +381,7 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       // together (a group index past the panel reads the current group and
       // stores nothing)
 #pragma unroll 1
-      for (int q0 = 0; q0 < kNB / kIB - 1; q0 += kGB) {
+      for (int q0 = 0; q0 < PW / kIB - 1; q0 += kGB) {
         cplx<T> od[kGB][kIB];
         int cgs[kGB], gws[kGB];
         bool ok[kGB];
@@ -385,7 +389,7 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
         for (int q = 0; q < kGB; ++q) {
           int g = q0 + q;
           g += (g >= cur) ? 1 : 0;
-          ok[q] = (q0 + q < kNB / kIB - 1) && g < ngroups;
+          ok[q] = (q0 + q < PW / kIB - 1) && g < ngroups;
           cgs[q] = (ok[q] ? g : cur) * kIB;
           gws[q] = min(kIB, cw - cgs[q]);
 #pragma unroll
@@ -401,7 +405,7 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
             if (isp) acc.re = acc.im = T(0);
 #pragma unroll
             for (int l = 0; l < kIB; ++l)
-              if (l < iw) cfma(acc, mm[l], Bo[l * kNB + cgs[q] + cc]);
+              if (l < iw) cfma(acc, mm[l], Bo[l * PW + cgs[q] + cc]);
             if (cc < gws[q]) x[(size_t)r * ld + c0 + cgs[q] + cc] = acc;
           }
         }
@@ -471,16 +475,32 @@ __global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
   __syncthreads();
   if (m == 0) return;   // the same for every thread
 
-  const int p0 = 2 * S, p1 = 2 * S + 1;
-  factor_panel<T>(x, d.ld, n, rows, m, piv, rowcol, p0, st, smem);
-  if (p1 * kNB < n) {
+  // Each 64-column half as two 32-column quarters joined by cross updates,
+  // then the halves joined the same way.  Order: Q0, Q0->Q1, Q1, Q1->Q0,
+  // L->R, Q2, Q2->Q3, Q3, Q3->Q2, R->L (one call site per kind of step).
+  const int ld = d.ld;
+  const int J0 = S * kNBO, J1 = J0 + kNB;
+#pragma unroll 1
+  for (int qi = 0; qi < 4; ++qi) {
+    const int c = J0 + 32 * qi;
+    if (c >= n) break;
+    if (qi == 2) {
+      cross_update<T, kNB, kNB>(x, ld, rows, m, piv, rowcol, J0, kNB, J1,
+                                min(kNB, n - J1), smem);
+      __syncthreads();
+    }
+    factor_panel<T, 32>(x, ld, n, rows, m, piv, rowcol, c, st, smem);
     __syncthreads();
-    inner_update<T>(x, d.ld, n, rows, m, piv, rowcol, p0, p1, smem);
-    __syncthreads();
-    factor_panel<T>(x, d.ld, n, rows, m, piv, rowcol, p1, st, smem);
-    __syncthreads();
-    inner_update<T>(x, d.ld, n, rows, m, piv, rowcol, p1, p0, smem);
+    const int dst = (qi & 1) ? c - 32 : c + 32;
+    if (dst < n) {
+      cross_update<T, 32, 32>(x, ld, rows, m, piv, rowcol, c, min(32, n - c),
+                              dst, min(32, n - dst), smem);
+      __syncthreads();
+    }
   }
+  if (J1 < n)
+    cross_update<T, kNB, kNB>(x, ld, rows, m, piv, rowcol, J1, min(kNB, n - J1),
+                              J0, kNB, smem);
 }
 
 // ------------------------------------------------------------------ gather
