@@ -30,7 +30,7 @@ PEAK_HBM_GBS = 8000.0
 # scaled by the same counter's reading for a plain 256 MiB copy (FETCH_SIZE x
 # 2.00, WRITE_SIZE x 1.00).  Reported only for that kernel and batch size.
 PROFILED_TRAFFIC = {"kernel": "fk::k_update<double, 2>", "batch": 757,
-                    "bytes_per_launch": 83.39e9}
+                    "bytes_per_launch": 82.58e9}
 
 
 def log(*a):
@@ -191,7 +191,10 @@ def main():
     # textbook 2 N^3 of a real inversion, four real products per complex one)
     flops_iter = 8.0 * n ** 3 * npts
     inversion_tflops = flops_iter * args.steps / (step_ms * 1e-3) / 1e12
-    # dominant kernel: the trailing update of each outer block, timed per launch
+    # dominant kernel: the trailing update of each outer block, timed per launch;
+    # its algorithmic flops count 8 real flops per complex multiply-add, while
+    # the kernel forms each complex product from three real ones, so its matrix
+    # cores execute 3/4 of that count ("mfma_frac")
     achieved = kc["flop"] / (kc["ms"] * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if args.mixed else PEAK_FP64_TFLOPS
     tuned = ctx.get_tuning()
@@ -223,6 +226,8 @@ def main():
                      "launches": kc["launches"],
                      "flops_per_launch": kc["flop"] / max(kc["launches"], 1),
                      "avg_launch_ms": kc["ms"] / max(kc["launches"], 1),
+                     "mfma_flops_per_launch": 0.75 * kc["flop"] / max(kc["launches"], 1),
+                     "mfma_frac": 0.75 * achieved / peak,
                      "whole_inversion_tflops": inversion_tflops,
                      "whole_inversion_frac": inversion_tflops / peak},
         "phases_ms_last_step": {k: round(v, 3) for k, v in tm_last.items()},
