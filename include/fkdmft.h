@@ -149,6 +149,29 @@ fk_status fk_get_current(const fk_ctx* ctx, double* t, double* j, double* n_t);
  * discrete contour).  m0: 2 N_t doubles (re, im interleaved). */
 fk_status fk_get_zeroth_moment(const fk_ctx* ctx, double* m0);
 
+/* Nonequilibrium density of states of the last lattice step's G_loc (Sec. II,
+ * eqs. gr_omega and dos_def): rho(T, w) = -Im G^R(T, w) / pi at the average
+ * times T = t_min + i dt for the n_T indices t_index[r] (0 <= i < N_t) and the
+ * n_w frequencies omega[q]; dos[r * n_w + q] (host arrays, caller-owned).
+ * G^R(t_a, t_b) = G_loc[2N_t - a][b] - G_loc[a][2N_t - b] for a >= b (G^> - G^<
+ * from the two real branches); the relative time runs over t_rel = 2 d dt,
+ * d = 0..D, D = min(i, N_t - 1 - i), by the trapezoid rule (weight 1/2 at d = 0
+ * and d = D), with no window function.  The integral of rho over one period of
+ * w (pi / dt) is exactly -Im m0(T).  FK_EINVAL for NULL arrays, n_T or n_w < 1,
+ * an index outside [0, N_t) or a non-finite frequency; FK_ESTATE before a
+ * lattice step. */
+fk_status fk_wigner_dos(const fk_ctx* ctx, int n_T, const int* t_index, int n_w,
+                        const double* omega, double* dos);
+/* Equal-time spectral moments of the local retarded function (Sec. II, moments
+ * paragraph) at T = t_min + i dt, i = t_index[r] (3 <= i <= N_t - 4): with
+ * f(s) = G^R(T + s/2, T - s/2), mu0 = i f(0), mu1 = -f'(0), mu2 = -i f''(0)
+ * (exact values 1, 0 and 1/2 + U^2/4 at half filling in the symmetric
+ * convention), the derivatives by one-sided second-order differences over
+ * s = 0, h, 2h, 3h with h = 2 dt.  mu: 6 n_T doubles, (re, im) of mu0, mu1, mu2
+ * for each index in turn.  Errors as for fk_wigner_dos. */
+fk_status fk_equal_time_moments(const fk_ctx* ctx, int n_T, const int* t_index,
+                                double* mu);
+
 /* Falicov-Kimball impurity update (eqs. effective_medium, dynamical_mean_field,
  * g_imp_solve and Dyson again), in right-weighted form A -> A W:
  *   g0inv = (G_loc W)^-1 + Sigma W

@@ -778,6 +778,66 @@ extern "C" fk_status fk_get_zeroth_moment(const fk_ctx* cc, double* m0) {
   return FK_OK;
 }
 
+namespace {
+// Device copies of small host arrays for the spectral functions: one
+// allocation per call (post-processing, outside the iteration), freed on return.
+struct CallBuffer {
+  void* p = nullptr;
+  ~CallBuffer() {
+    if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+extern "C" fk_status fk_wigner_dos(const fk_ctx* cc, int n_T, const int* t_index,
+                                   int n_w, const double* omega, double* dos) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c || !t_index || !omega || !dos || n_T < 1 || n_w < 1) return FK_EINVAL;
+  const int n_t = c->ci.n_t, n = c->ci.n_c;
+  for (int r = 0; r < n_T; ++r)
+    if (t_index[r] < 0 || t_index[r] >= n_t)
+      return set_err(c, FK_EINVAL, "time index %d outside [0, N_t)", t_index[r]);
+  for (int q = 0; q < n_w; ++q)
+    if (!std::isfinite(omega[q])) return set_err(c, FK_EINVAL, "non-finite frequency");
+  if (!c->have_gloc) return set_err(c, FK_ESTATE, "no lattice step yet");
+  const size_t bi = sizeof(int) * (size_t)n_T, bw = sizeof(double) * (size_t)n_w;
+  const size_t bo = sizeof(double) * (size_t)n_T * n_w;
+  const size_t off_w = (bi + 255) / 256 * 256, off_o = off_w + (bw + 255) / 256 * 256;
+  CallBuffer buf;
+  HIPCHK(c, hipMalloc(&buf.p, off_o + bo));
+  char* base = static_cast<char*>(buf.p);
+  HIPCHK(c, hipMemcpyAsync(base, t_index, bi, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(base + off_w, omega, bw, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, launch_wigner_dos(c->d_gloc, n_t, n, c->c.dt, reinterpret_cast<int*>(base),
+                              n_T, reinterpret_cast<double*>(base + off_w), n_w,
+                              reinterpret_cast<double*>(base + off_o), c->st));
+  HIPCHK(c, hipMemcpyAsync(dos, base + off_o, bo, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return FK_OK;
+}
+
+extern "C" fk_status fk_equal_time_moments(const fk_ctx* cc, int n_T, const int* t_index,
+                                           double* mu) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c || !t_index || !mu || n_T < 1) return FK_EINVAL;
+  const int n_t = c->ci.n_t, n = c->ci.n_c;
+  for (int r = 0; r < n_T; ++r)
+    if (t_index[r] < 3 || t_index[r] > n_t - 4)
+      return set_err(c, FK_EINVAL, "time index %d outside [3, N_t - 4]", t_index[r]);
+  if (!c->have_gloc) return set_err(c, FK_ESTATE, "no lattice step yet");
+  const size_t bi = sizeof(int) * (size_t)n_T, off_o = (bi + 255) / 256 * 256;
+  const size_t bo = sizeof(c64) * 3 * (size_t)n_T;
+  CallBuffer buf;
+  HIPCHK(c, hipMalloc(&buf.p, off_o + bo));
+  char* base = static_cast<char*>(buf.p);
+  HIPCHK(c, hipMemcpyAsync(base, t_index, bi, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, launch_moments(c->d_gloc, n_t, n, c->c.dt, reinterpret_cast<int*>(base), n_T,
+                           reinterpret_cast<c64*>(base + off_o), c->st));
+  HIPCHK(c, hipMemcpyAsync(mu, base + off_o, bo, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return FK_OK;
+}
+
 extern "C" fk_status fk_impurity_update(fk_ctx* c, double* max_dsigma_out) {
   if (!c) return FK_EINVAL;
   return impurity(c, max_dsigma_out);

@@ -466,7 +466,7 @@ extern "C" fk_status fk_batch_create(int n_inst, const fk_contour* contours,
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->aux.evN, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->aux.evP, hipEventDisableTiming);
   // set the kernels' LDS attribute outside any capture
-  if (e == hipSuccess) e = gje_panel<double>(nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, b->st);
+  if (e == hipSuccess) e = gje_panel<double>(nullptr, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, b->st);
   if (e != hipSuccess) {
     fk_batch_destroy(b);
     return FK_EDEVICE;

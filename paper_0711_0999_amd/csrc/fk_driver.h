@@ -63,6 +63,7 @@ template <typename T> struct Batch {
   // all other columns ("big"), matrix-major so a prefix serves fewer matrices
   std::vector<int> offN, cntN, offB, cntB;
   int nouter = 0;
+  int nmax = 0;       // largest matrix (selects the panel shape)
   // uneven batches (matrices of different sizes packed back to back): item
   // totals per step, total pivot ints, and capacities of the buffers
   bool uniform = true;
@@ -116,6 +117,7 @@ hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
   b.variant = variant;
   b.cap = cap;
   b.n = n;
+  b.nmax = n;
   b.ld = n;
   b.stride = (size_t)n * n;
   b.nouter = (n + kNBO - 1) / kNBO;
@@ -204,6 +206,8 @@ hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
     nouter = std::max(nouter, (n[m] + kNBO - 1) / kNBO);
   }
   b.nouter = nouter;
+  b.nmax = 0;
+  for (int m = 0; m < nm; ++m) b.nmax = std::max(b.nmax, n[m]);
   b.nints = io;
   hipError_t e;
   if ((e = grow(&b.x, &b.x_cap, xo)) != hipSuccess) return e;
@@ -292,7 +296,7 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
   if (!status && (e = fill_int(b.status, 0, (size_t)nmat, st)) != hipSuccess) return e;
   if (ev_steps && (e = hipEventRecord(ev_steps[0], st)) != hipSuccess) return e;
   int nl = 0;
-  if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, 0, stat, st)) !=
+  if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, b.nmax, 0, stat, st)) !=
       hipSuccess)
     return e;
   ++nl;
@@ -317,7 +321,7 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
         if ((e = hipEventRecord(ax.evN, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(ax.st2, ax.evN, 0)) != hipSuccess) return e;
       }
-      if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, S + 1, stat,
+      if ((e = gje_panel<T>(b.x, b.piv, b.rowcol, b.descs, nmat, b.nmax, S + 1, stat,
                             ps)) != hipSuccess)
         return e;
       ++nl;

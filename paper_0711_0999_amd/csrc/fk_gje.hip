@@ -70,9 +70,14 @@ __device__ inline void cfma(cplx<T>& acc, const cplx<T>& a, const cplx<T>& b) {
 }
 
 constexpr int kPW = kPanelThreads / 64;          // waves of the panel kernel
-constexpr int kRPT = kMaxN / kPanelThreads;      // panel rows per thread
+// Panel shapes: rows per thread and register block, (4, 8) up to kSmallN
+// rows, (kMaxN / kPanelThreads, 4) beyond (fewer columns per register block
+// keep the larger row count in registers).
+constexpr int kSmallN = 2048;
+constexpr int kRPTs = kSmallN / kPanelThreads, kIBs = kIB;
+constexpr int kRPTl = kMaxN / kPanelThreads, kIBl = 4;
 constexpr int kPitch = kNB + 1;                  // padded LDS row (elements)
-static_assert(kMaxN % kPanelThreads == 0, "kMaxN");
+static_assert(kMaxN % kPanelThreads == 0 && kSmallN % kPanelThreads == 0, "kMaxN");
 static_assert(kNBO == 2 * kNB && kTile == kNB, "block sizes");
 
 // ------------------------------------------------------ panel: cross update
@@ -81,7 +86,7 @@ static_assert(kNBO == 2 * kNB && kTile == kNB, "block sizes");
 // pivot rows in [c0, c0 + cw) (read before any write: this workgroup owns the
 // matrix).  KW >= w and CW >= cw are the compile-time widths (32 or 64).  The
 // kPW waves form (kPW / (CW/16)) x (CW/16) blocks of (16 RB) x 16 over each
-// 64-row tile.
+// tile of TRW rows (at least 64).
 template <typename T, int KW, int CW>
 __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
                              const int* __restrict__ rows, int m,
@@ -89,14 +94,17 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
                              const int* __restrict__ rowcol, int j0, int w,
                              int c0, int cw, unsigned char* smem) {
   typedef typename Mfma<T>::v4 v4;
-  constexpr int NCB = CW / 16, NRW = kPW / NCB, RB = kTile / (16 * NRW);
-  static_assert(NCB * NRW == kPW && RB >= 1 && 16 * RB * NRW == kTile, "waves");
+  constexpr int NCB = CW / 16, NRW = kPW / NCB;
+  constexpr int RB = 16 * NRW >= 64 ? 1 : 64 / (16 * NRW);
+  constexpr int TRW = 16 * RB * NRW;
+  static_assert(NCB * NRW == kPW && TRW <= kNB + kTile, "waves");
   constexpr int KP = KW + 1, CP = CW + 1;
   cplx<T>* Bs = reinterpret_cast<cplx<T>*>(smem);   // [KW][CP]
-  cplx<T>* Ms = Bs + KW * CP;                        // [kTile][KP]
+  cplx<T>* Ms = Bs + KW * CP;                        // [TRW][KP]
   constexpr int kLB = KW * CW / kPanelThreads;      // B elements per thread
-  constexpr int kLM = kTile * KW / kPanelThreads;   // M elements per thread
-  static_assert(kLB * kPanelThreads == KW * CW && kLM * kPanelThreads == kTile * KW, "loads");
+  constexpr int kLM = TRW * KW / kPanelThreads;     // M elements per thread
+  static_assert(kLB * kPanelThreads == KW * CW && kLM * kPanelThreads == TRW * KW, "loads");
+  static_assert(KW * CP + TRW * KP <= (kNB + kTile) * kPitch, "LDS");
   const int tid = threadIdx.x;
   {
     int pr[kLB];
@@ -124,7 +132,7 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
   const int wr = wave / NCB, wc = wave % NCB;
   const int li = lane & 15, lk = lane >> 4;
   const int col = 16 * wc + li;
-  for (int r0 = 0; r0 < m; r0 += kTile) {
+  for (int r0 = 0; r0 < m; r0 += TRW) {
     __syncthreads();
     cplx<T> mv[kLM];
 #pragma unroll
@@ -191,68 +199,70 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
   }
 }
 
-// Column groups updated per batch of loads in the panel's rank-kIB updates
-// (bounded by registers: kIB complex values per group).
+// Column groups of 8 columns updated per batch of loads in the panel's rank-IB
+// updates (bounded by registers: IB complex values per group; twice the
+// groups for IB = 4).
 template <typename T> struct GroupBatch { static constexpr int value = 4; };
 template <> struct GroupBatch<float> { static constexpr int value = 7; };
 
 // ---------------------------------------------------- panel: factorization
 // Eliminate the PW (32 or 64) columns starting at c0 on the listed rows
 // rows[0, m) (the rows not pivoted before this outer block) with partial
-// pivoting.  Thread tid owns list entries tid + i * kPanelThreads; the list is
-// in ascending row order, so a tie of pivot keys goes to the lowest row index.
-template <typename T, int PW>
+// pivoting, IB columns at a time in registers.  Thread tid owns list entries
+// tid + i * kPanelThreads, i < RPT; the list is in ascending row order, so a
+// tie of pivot keys goes to the lowest row index.
+template <typename T, int PW, int RPT, int IB>
 __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, int n,
                              const int* __restrict__ rows, int m,
                              int* __restrict__ piv, int* __restrict__ rowcol,
                              int c0, int* __restrict__ status,
                              unsigned char* smem) {
-  static_assert(PW % kIB == 0 && PW <= kNB, "panel width");
-  cplx<T>* Bo = reinterpret_cast<cplx<T>*>(smem);   // [kIB][PW]
-  cplx<T>* prow = Bo + kIB * PW;                     // [kIB]
-  T* redv = reinterpret_cast<T*>(prow + kIB);        // [kPW]
+  static_assert(PW % IB == 0 && PW <= kNB, "panel width");
+  cplx<T>* Bo = reinterpret_cast<cplx<T>*>(smem);   // [IB][PW]
+  cplx<T>* prow = Bo + IB * PW;                     // [IB]
+  T* redv = reinterpret_cast<T*>(prow + IB);        // [kPW]
   int* redi = reinterpret_cast<int*>(redv + kPW);    // [kPW]
-  int* pvt = redi + kPW;                             // [kIB]
+  int* pvt = redi + kPW;                             // [IB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cw = min(PW, n - c0);
   const T inf_key = big_value<T>();
-  constexpr int kGB = GroupBatch<T>::value;
+  constexpr int kGB = GroupBatch<T>::value * 8 / IB;
 
-  bool pvd[kRPT];
-  int rr[kRPT];
+  bool pvd[RPT];
+  int rr[RPT];
 #pragma unroll
-  for (int i = 0; i < kRPT; ++i) {
+  for (int i = 0; i < RPT; ++i) {
     const int e = tid + i * kPanelThreads;
     rr[i] = rows[min(e, m - 1)];
     pvd[i] = (e < m) ? (rowcol[rr[i]] >= 0) : true;
   }
-  const int ngroups = (cw + kIB - 1) / kIB;
+  const int ngroups = (cw + IB - 1) / IB;
 
-  for (int b0 = 0; b0 < cw; b0 += kIB) {
-    const int iw = min(kIB, cw - b0);
-    cplx<T> v[kRPT][kIB];
+  for (int b0 = 0; b0 < cw; b0 += IB) {
+    const int iw = min(IB, cw - b0);
+    cplx<T> v[RPT][IB];
 #pragma unroll
-    for (int i = 0; i < kRPT; ++i) {
+    for (int i = 0; i < RPT; ++i) {
 #pragma unroll
-      for (int l = 0; l < kIB; ++l)
+      for (int l = 0; l < IB; ++l)
         v[i][l] = x[(size_t)rr[i] * ld + c0 + b0 + min(l, iw - 1)];
     }
 #pragma unroll
-    for (int i = 0; i < kRPT; ++i) {
+    for (int i = 0; i < RPT; ++i) {
       const int e = tid + i * kPanelThreads;
 #pragma unroll
-      for (int l = 0; l < kIB; ++l)
+      for (int l = 0; l < IB; ++l)
         if (!(e < m && l < iw)) v[i][l].re = v[i][l].im = T(0);
     }
 #pragma unroll
-    for (int l = 0; l < kIB; ++l) {
+    for (int l = 0; l < IB; ++l) {
       if (l >= iw) break;
       // ---- pivot search: largest |re|+|im| among unpivoted rows (bidx is
       // a list index)
       T best = T(-1);
       int bidx = INT_MAX;
 #pragma unroll
-      for (int i = 0; i < kRPT; ++i) {
+      for (int i = 0; i < RPT; ++i) {
         const int e = tid + i * kPanelThreads;
         if (e < m && !pvd[i]) {
           T a = fabs(v[i][l].re) + fabs(v[i][l].im);
@@ -298,10 +308,10 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       if ((pe % kPanelThreads) == tid) {
         const int i = pe / kPanelThreads;
 #pragma unroll
-        for (int ii = 0; ii < kRPT; ++ii)
+        for (int ii = 0; ii < RPT; ++ii)
           if (ii == i) {
 #pragma unroll
-            for (int l2 = 0; l2 < kIB; ++l2) prow[l2] = v[ii][l2];
+            for (int l2 = 0; l2 < IB; ++l2) prow[l2] = v[ii][l2];
             pvd[ii] = true;
           }
         piv[col] = p;
@@ -315,20 +325,20 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       cplx<T> inv;
       inv.re = pv.re / den;
       inv.im = -pv.im / den;
-      cplx<T> ps[kIB];
+      cplx<T> ps[IB];
 #pragma unroll
-      for (int l2 = 0; l2 < kIB; ++l2) ps[l2] = cmul(prow[l2], inv);
+      for (int l2 = 0; l2 < IB; ++l2) ps[l2] = cmul(prow[l2], inv);
       ps[l] = inv;
 #pragma unroll
-      for (int i = 0; i < kRPT; ++i) {
+      for (int i = 0; i < RPT; ++i) {
         const int e = tid + i * kPanelThreads;
         if (e == pe) {
 #pragma unroll
-          for (int l2 = 0; l2 < kIB; ++l2) v[i][l2] = ps[l2];
+          for (int l2 = 0; l2 < IB; ++l2) v[i][l2] = ps[l2];
         } else {
           const cplx<T> m = v[i][l];
 #pragma unroll
-          for (int l2 = 0; l2 < kIB; ++l2)
+          for (int l2 = 0; l2 < IB; ++l2)
             if (l2 != l) {
               v[i][l2].re -= m.re * ps[l2].re - m.im * ps[l2].im;
               v[i][l2].im -= m.re * ps[l2].im + m.im * ps[l2].re;
@@ -342,15 +352,15 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
     }
     // ---- write the eliminated block back; old pivot rows of the other columns
 #pragma unroll
-    for (int i = 0; i < kRPT; ++i) {
+    for (int i = 0; i < RPT; ++i) {
       const int e = tid + i * kPanelThreads;
       if (e < m) {
 #pragma unroll
-        for (int l = 0; l < kIB; ++l)
+        for (int l = 0; l < IB; ++l)
           if (l < iw) x[(size_t)rr[i] * ld + c0 + b0 + l] = v[i][l];
       }
     }
-    for (int e = tid; e < kIB * PW; e += kPanelThreads) {
+    for (int e = tid; e < IB * PW; e += kPanelThreads) {
       const int l = e / PW, c = e % PW;
       const bool ok = l < iw && c < cw && (c < b0 || c >= b0 + iw);
       cplx<T> t = x[(size_t)pvt[min(l, iw - 1)] * ld + c0 + min(c, cw - 1)];
@@ -362,49 +372,49 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
     // this thread owns and has just written: each row's eliminated values are
     // read back once (same thread, program order) and applied to every other
     // group of the row.
-    const int cur = b0 / kIB;
-    int pv0[kIB];
+    const int cur = b0 / IB;
+    int pv0[IB];
 #pragma unroll
-    for (int l = 0; l < kIB; ++l) pv0[l] = (l < iw) ? pvt[l] : -1;
+    for (int l = 0; l < IB; ++l) pv0[l] = (l < iw) ? pvt[l] : -1;
 #pragma unroll 1
-    for (int i = 0; i < kRPT; ++i) {
+    for (int i = 0; i < RPT; ++i) {
       const int e = tid + i * kPanelThreads;
       if (e >= m) break;
       const int r = rows[e];
       bool isp = false;
 #pragma unroll
-      for (int l = 0; l < kIB; ++l) isp |= (pv0[l] == r);
-      cplx<T> mm[kIB];
+      for (int l = 0; l < IB; ++l) isp |= (pv0[l] == r);
+      cplx<T> mm[IB];
 #pragma unroll
-      for (int l = 0; l < kIB; ++l) mm[l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
+      for (int l = 0; l < IB; ++l) mm[l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
       // the other groups in batches of kGB whose loads are all in flight
       // together (a group index past the panel reads the current group and
       // stores nothing)
 #pragma unroll 1
-      for (int q0 = 0; q0 < PW / kIB - 1; q0 += kGB) {
-        cplx<T> od[kGB][kIB];
+      for (int q0 = 0; q0 < PW / IB - 1; q0 += kGB) {
+        cplx<T> od[kGB][IB];
         int cgs[kGB], gws[kGB];
         bool ok[kGB];
 #pragma unroll
         for (int q = 0; q < kGB; ++q) {
           int g = q0 + q;
           g += (g >= cur) ? 1 : 0;
-          ok[q] = (q0 + q < PW / kIB - 1) && g < ngroups;
-          cgs[q] = (ok[q] ? g : cur) * kIB;
-          gws[q] = min(kIB, cw - cgs[q]);
+          ok[q] = (q0 + q < PW / IB - 1) && g < ngroups;
+          cgs[q] = (ok[q] ? g : cur) * IB;
+          gws[q] = min(IB, cw - cgs[q]);
 #pragma unroll
-          for (int cc = 0; cc < kIB; ++cc)
+          for (int cc = 0; cc < IB; ++cc)
             od[q][cc] = x[(size_t)r * ld + c0 + cgs[q] + min(cc, gws[q] - 1)];
         }
 #pragma unroll
         for (int q = 0; q < kGB; ++q) {
           if (!ok[q]) continue;
 #pragma unroll
-          for (int cc = 0; cc < kIB; ++cc) {
+          for (int cc = 0; cc < IB; ++cc) {
             cplx<T> acc = od[q][cc];
             if (isp) acc.re = acc.im = T(0);
 #pragma unroll
-            for (int l = 0; l < kIB; ++l)
+            for (int l = 0; l < IB; ++l)
               if (l < iw) cfma(acc, mm[l], Bo[l * PW + cgs[q] + cc]);
             if (cc < gws[q]) x[(size_t)r * ld + c0 + cgs[q] + cc] = acc;
           }
@@ -425,14 +435,15 @@ template <typename T> __host__ __device__ constexpr size_t panel_body_bytes() {
                : sizeof(cplx<T>) * (kIB * kNB + kIB) + kPW * sizeof(T) +
                      kPW * sizeof(int) + kIB * sizeof(int)) + 15) / 16 * 16;
 }
-template <typename T> static size_t panel_lds_bytes() {
-  return panel_body_bytes<T>() + sizeof(int) * (size_t)kMaxN;
+template <typename T> static size_t panel_lds_bytes(int rpt) {
+  return panel_body_bytes<T>() + sizeof(int) * (size_t)rpt * kPanelThreads;
 }
 
 // Outer block S of one matrix.  Rows pivoted in earlier blocks take no part:
 // their columns of this block follow from the block's pivot rows afterwards
 // (k_fix), so the panel reads and writes only the n - S kNBO remaining rows.
-template <typename T>
+// RPT kPanelThreads >= n rows; IB columns eliminated in registers at a time.
+template <typename T, int RPT, int IB>
 __global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
     cplx<T>* __restrict__ xbuf, int* __restrict__ pivbuf,
     int* __restrict__ rowcolbuf, const MatDesc* __restrict__ descs, int S,
@@ -448,20 +459,20 @@ __global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
 
   // list the unpivoted rows in ascending order (wave ballots, then offsets)
   int* rows = reinterpret_cast<int*>(smem + panel_body_bytes<T>());
-  int* cnt = reinterpret_cast<int*>(smem);   // [kRPT][kPW], before the panel
+  int* cnt = reinterpret_cast<int*>(smem);   // [RPT][kPW], before the panel
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  unsigned long long bal[kRPT];
+  unsigned long long bal[RPT];
 #pragma unroll
-  for (int i = 0; i < kRPT; ++i) {
+  for (int i = 0; i < RPT; ++i) {
     const int r = tid + i * kPanelThreads;
     bal[i] = __ballot(r < n && rowcol[min(r, n - 1)] < 0);
     if (lane == 0) cnt[i * kPW + wave] = (int)__popcll(bal[i]);
   }
   __syncthreads();
   int m = 0;   // n - S kNBO unless earlier blocks failed to pivot
-  int pos[kRPT];
+  int pos[RPT];
 #pragma unroll
-  for (int i = 0; i < kRPT; ++i) {
+  for (int i = 0; i < RPT; ++i) {
     int before = 0;
 #pragma unroll
     for (int wv = 0; wv < kPW; ++wv) before += (wv < wave) ? cnt[i * kPW + wv] : 0;
@@ -470,7 +481,7 @@ __global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
     for (int wv = 0; wv < kPW; ++wv) m += cnt[i * kPW + wv];
   }
 #pragma unroll
-  for (int i = 0; i < kRPT; ++i)
+  for (int i = 0; i < RPT; ++i)
     if ((bal[i] >> lane) & 1ull) rows[pos[i]] = tid + i * kPanelThreads;
   __syncthreads();
   if (m == 0) return;   // the same for every thread
@@ -489,7 +500,7 @@ __global__ __launch_bounds__(kPanelThreads, 1) void k_outer_panel(
                                 min(kNB, n - J1), smem);
       __syncthreads();
     }
-    factor_panel<T, 32>(x, ld, n, rows, m, piv, rowcol, c, st, smem);
+    factor_panel<T, 32, RPT, IB>(x, ld, n, rows, m, piv, rowcol, c, st, smem);
     __syncthreads();
     const int dst = (qi & 1) ? c - 32 : c + 32;
     if (dst < n) {
@@ -857,19 +868,28 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
 // --------------------------------------------------------------- launchers
 template <typename T>
 hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
-                     int nmat, int S, int* status, hipStream_t st) {
+                     int nmat, int nmax, int S, int* status, hipStream_t st) {
   static bool attr_set = false;
-  const size_t lds = panel_lds_bytes<T>();
+  const size_t lds_s = panel_lds_bytes<T>(kRPTs), lds_l = panel_lds_bytes<T>(kRPTl);
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_outer_panel<T>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        reinterpret_cast<const void*>(&k_outer_panel<T, kRPTs, kIBs>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(&k_outer_panel<T, kRPTl, kIBl>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_l);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   if (nmat <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_outer_panel<T>, dim3(nmat), dim3(kPanelThreads), lds, st,
-                     x, piv, rowcol, d, S, status);
+  if (nmax > kMaxN) return hipErrorInvalidValue;
+  if (nmax <= kSmallN)
+    hipLaunchKernelGGL((k_outer_panel<T, kRPTs, kIBs>), dim3(nmat), dim3(kPanelThreads),
+                       lds_s, st, x, piv, rowcol, d, S, status);
+  else
+    hipLaunchKernelGGL((k_outer_panel<T, kRPTl, kIBl>), dim3(nmat), dim3(kPanelThreads),
+                       lds_l, st, x, piv, rowcol, d, S, status);
   return hipGetLastError();
 }
 
@@ -910,7 +930,7 @@ hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
 
 #define FK_INST(T)                                                            \
   template hipError_t gje_panel<T>(cplx<T>*, int*, int*, const MatDesc*, int, \
-                                   int, int*, hipStream_t);                   \
+                                   int, int, int*, hipStream_t);              \
   template hipError_t gje_gather<T>(const cplx<T>*, cplx<T>*, const int*,     \
                                     const MatDesc*, int, int, hipStream_t);   \
   template hipError_t gje_fix<T>(cplx<T>*, const cplx<T>*, const int*,       \

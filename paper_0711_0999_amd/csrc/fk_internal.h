@@ -40,7 +40,7 @@ constexpr int kKC = 16;          // K chunk of the trailing update
 constexpr int kIB = 8;           // panel columns eliminated in registers at once
 constexpr int kPanelThreads = 512;
 constexpr int kGemmThreads = 256;
-constexpr int kMaxN = 2048;      // largest matrix the inversion supports
+constexpr int kMaxN = 5120;      // largest matrix the inversion supports
 
 // Outer step S of the blocked in-place Gauss-Jordan inversion, pieces:
 //   panel   one workgroup per matrix factors the outer block [S*kNBO, +kNBO)
@@ -49,7 +49,7 @@ constexpr int kMaxN = 2048;      // largest matrix the inversion supports
 //   update  C <- mask(C) + M B on the listed tiles (K = outer block width)
 template <typename T>
 hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
-                     int nmat, int S, int* status, hipStream_t st);
+                     int nmat, int nmax, int S, int* status, hipStream_t st);
 template <typename T>
 hipError_t gje_gather(const cplx<T>* x, cplx<T>* bbuf, const int* piv,
                       const MatDesc* d, int nmat, int S, hipStream_t st);

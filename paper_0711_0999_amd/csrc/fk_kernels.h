@@ -42,6 +42,14 @@ hipError_t launch_current(const cplx<TI>* xbuf, size_t mat_stride, int ld,
                           int n, double* cur, hipStream_t st);
 hipError_t launch_maxabs(const c64* a, const c64* b, size_t total,
                          unsigned long long* key, hipStream_t st);
+// Nonequilibrium DOS rho(t_i, w) (dos[r * n_w + q], i = tix[r]) and equal-time
+// moments mu_m(t_i) (mu[3 r + m]) of the local G on the contour; the time
+// indices must satisfy 0 <= i < N_t (DOS) and 3 <= i <= N_t - 4 (moments).
+hipError_t launch_wigner_dos(const c64* g, int n_t, int n, double dt, const int* tix,
+                             int n_T, const double* w, int n_w, double* dos,
+                             hipStream_t st);
+hipError_t launch_moments(const c64* g, int n_t, int n, double dt, const int* tix,
+                          int n_T, c64* mu, hipStream_t st);
 hipError_t launch_equal_time(const c64* g, int n_t, int n, c64* less, c64* greater,
                              hipStream_t st);
 hipError_t launch_right_weight(const c64* src, const c64* w, c64* dst, int ld,

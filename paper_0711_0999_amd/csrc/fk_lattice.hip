@@ -195,6 +195,90 @@ hipError_t launch_equal_time(const c64* g, int n_t, int n, c64* less, c64* great
   return hipGetLastError();
 }
 
+// ------------------------------------------------ spectral functions ------
+// Retarded pair f_d = G^R(t_{i+d}, t_{i-d}) = G^> - G^< of the local G on the
+// contour, with G^>(t_a, t_b) = G[p(a)][b], G^<(t_a, t_b) = G[a][p(b)] and
+// p(k) = 2 N_t - k (Sec. II: the retarded function from the two real branches).
+__device__ inline c64 retarded_pair(const c64* __restrict__ g, int n_t, int n,
+                                    int i, int d) {
+  const int a = i + d, b = i - d;
+  const c64 gg = g[(size_t)(2 * n_t - a) * n + b];
+  const c64 gl = g[(size_t)a * n + (2 * n_t - b)];
+  c64 f;
+  f.re = gg.re - gl.re;
+  f.im = gg.im - gl.im;
+  return f;
+}
+
+// Nonequilibrium DOS (Sec. II, eqs. gr_omega and dos_def) at the average times
+// T = t_i, i = tix[r], and the frequencies w[q]: one thread per frequency and
+// time (times strided over the grid's y dimension),
+//   rho = -(h / pi) Im sum_{d=0}^{D} c_d e^{i w d h} f_d,
+// h = 2 dt, D = min(i, N_t - 1 - i), trapezoid weights c_0 = c_D = 1/2 (c_0 =
+// 1/2 alone when D = 0), 1 in between.
+__global__ void k_wigner_dos(const c64* __restrict__ g, int n_t, int n, double h,
+                             const int* __restrict__ tix, int n_T,
+                             const double* __restrict__ w, int n_w,
+                             double* __restrict__ dos) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_w) return;
+  const double om = w[q];
+  for (int r = blockIdx.y; r < n_T; r += gridDim.y) {
+    const int i = tix[r];
+    const int dmax = min(i, n_t - 1 - i);
+    double acc = 0.0;
+    for (int d = 0; d <= dmax; ++d) {
+      const c64 f = retarded_pair(g, n_t, n, i, d);
+      double sn, cs;
+      sincos(om * (d * h), &sn, &cs);
+      const double c = (d == 0 || d == dmax) ? 0.5 : 1.0;
+      acc += c * (sn * f.re + cs * f.im);
+    }
+    dos[(size_t)r * n_w + q] = -h * acc / 3.14159265358979323846;
+  }
+}
+
+// Equal-time moments (Sec. II, moments paragraph) at T = t_i, i = tix[r]
+// (3 <= i <= N_t - 4): with f_d as above and h = 2 dt,
+//   mu0 = i f_0,  mu1 = -(-3 f_0 + 4 f_1 - f_2) / (2 h),
+//   mu2 = -i (2 f_0 - 5 f_1 + 4 f_2 - f_3) / h^2;
+// mu[3 r + m] = mu_m.
+__global__ void k_moments(const c64* __restrict__ g, int n_t, int n, double h,
+                          const int* __restrict__ tix, int n_T, c64* __restrict__ mu) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_T) return;
+  const int i = tix[r];
+  const c64 f0 = retarded_pair(g, n_t, n, i, 0), f1 = retarded_pair(g, n_t, n, i, 1);
+  const c64 f2 = retarded_pair(g, n_t, n, i, 2), f3 = retarded_pair(g, n_t, n, i, 3);
+  c64 m0, m1, m2;
+  m0.re = -f0.im;
+  m0.im = f0.re;
+  m1.re = -(-3.0 * f0.re + 4.0 * f1.re - f2.re) / (2.0 * h);
+  m1.im = -(-3.0 * f0.im + 4.0 * f1.im - f2.im) / (2.0 * h);
+  const double d2r = (2.0 * f0.re - 5.0 * f1.re + 4.0 * f2.re - f3.re) / (h * h);
+  const double d2i = (2.0 * f0.im - 5.0 * f1.im + 4.0 * f2.im - f3.im) / (h * h);
+  m2.re = d2i;     // -i (d2r + i d2i)
+  m2.im = -d2r;
+  mu[3 * r] = m0;
+  mu[3 * r + 1] = m1;
+  mu[3 * r + 2] = m2;
+}
+
+hipError_t launch_wigner_dos(const c64* g, int n_t, int n, double dt, const int* tix,
+                             int n_T, const double* w, int n_w, double* dos,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_wigner_dos, dim3((n_w + 127) / 128, n_T < 4096 ? n_T : 4096),
+                     dim3(128), 0, st, g, n_t, n, 2.0 * dt, tix, n_T, w, n_w, dos);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const c64* g, int n_t, int n, double dt, const int* tix,
+                          int n_T, c64* mu, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments, dim3((n_T + 127) / 128), dim3(128), 0, st, g, n_t, n,
+                     2.0 * dt, tix, n_T, mu);
+  return hipGetLastError();
+}
+
 // -------------------------------------------------------------- norms ------
 // bits of the max of |a - b| (or |a| when b == nullptr) as an unsigned 64-bit
 // key: non-negative doubles order like their bit patterns, NaN above +Inf.

@@ -4,8 +4,10 @@ The paper extrapolates its dt-dependent results with Lagrange polynomials in
 dt (Sec. II, the accuracy discussion of the results).  Here several contours
 that differ only in the step h (dt = dtau = h) are solved together in one
 multi-instance sweep (uneven N_c in shared batched launches, fk_batch); the
-current j(t), the filling n(t) and the zeroth moment m0(t) are read on the
-coarsest time grid, and their value at h = 0 is the Lagrange combination
+current j(t), the filling n(t), the zeroth moment m0(t) and the equal-time
+spectral moments mu0, mu1, mu2 (fk_equal_time_moments, on the coarse times
+3..N_t - 4 of the coarsest grid) are read on the coarsest time grid, and their
+value at h = 0 is the Lagrange combination
 sum_k w_k f_k with w_k = prod_{m != k} h_m / (h_m - h_k).  The extrapolation is
 host arithmetic on a few vectors of N_t values; every DMFT step runs in the
 library's kernels.
@@ -30,8 +32,9 @@ def step_sweep(t_min, t_max, beta, steps, model, tol=1e-10, max_iter=200,
                use_graph=True):
     """Solve the contour t in [t_min, t_max], beta with dt = dtau = h for every h
     in steps (the coarsest first; each a whole multiple of the finest) in one
-    fk_batch, to delta < tol.  Returns the coarse times, per-step j, n, m0 on
-    that grid, their extrapolation to h = 0, and the iteration counts."""
+    fk_batch, to delta < tol.  Returns the coarse times, per-step j, n, m0 and
+    mu (complex [3, N_t - 6], at the coarse times t_mu) on that grid, their
+    extrapolation to h = 0, and the iteration counts."""
     steps = [float(h) for h in steps]
     h0 = max(steps)
     inst = [dict(t_min=t_min, t_max=t_max, dt=h, dtau=h, beta=beta, **model) for h in steps]
@@ -51,8 +54,10 @@ def step_sweep(t_min, t_max, beta, steps, model, tol=1e-10, max_iter=200,
             if h == h0:
                 t_coarse = t
             nc = int(round((t_max - t_min) / h0))
-            per[h] = dict(j=j[::s][:nc], n=n[::s][:nc], m0=m0[::s][:nc])
+            mu = c.moments(np.arange(3, nc - 3) * s)
+            per[h] = dict(j=j[::s][:nc], n=n[::s][:nc], m0=m0[::s][:nc], mu=mu)
     w = lagrange_weights(steps)
-    ext = {q: sum(w[k] * per[h][q] for k, h in enumerate(steps)) for q in ("j", "n", "m0")}
-    return dict(t=t_coarse, per_step=per, extrapolated=ext, weights=w,
-                iters=[int(v) for v in r["iters"]])
+    ext = {q: sum(w[k] * per[h][q] for k, h in enumerate(steps))
+           for q in ("j", "n", "m0", "mu")}
+    return dict(t=t_coarse, t_mu=t_coarse[3:nc - 3], per_step=per, extrapolated=ext,
+                weights=w, iters=[int(v) for v in r["iters"]])

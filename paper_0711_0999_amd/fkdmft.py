@@ -85,6 +85,8 @@ SIGNATURES = {
     "fk_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(Tuning)]),
     "fk_low_iterations": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
     "fk_get_zeroth_moment": (ctypes.c_int, [_vp, _dp]),
+    "fk_wigner_dos": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _dp, _dp]),
+    "fk_equal_time_moments": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _dp]),
     "fk_get_point_green": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "fk_set_kernel_clock": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fk_kernel_clock": (ctypes.c_int, [_vp, _dp]),
@@ -301,6 +303,24 @@ class Context:
         m = np.zeros(2 * self.n_t)
         self._check(self._lib.fk_get_zeroth_moment(self._h, _dptr(m)), "fk_get_zeroth_moment")
         return m.view(np.complex128)
+
+    def wigner_dos(self, t_index, omega):
+        """rho(T_i, w) at T_i = t_min + i dt for the time indices and the
+        frequencies; array [len(t_index), len(omega)]."""
+        ti = np.ascontiguousarray(t_index, dtype=np.int32)
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        out = np.zeros((len(ti), len(om)))
+        self._check(self._lib.fk_wigner_dos(self._h, len(ti), ti.ctypes.data, len(om),
+                                            _dptr(om), _dptr(out)), "fk_wigner_dos")
+        return out
+
+    def moments(self, t_index):
+        """(mu0, mu1, mu2) at the time indices: complex array [3, len(t_index)]."""
+        ti = np.ascontiguousarray(t_index, dtype=np.int32)
+        out = np.zeros(6 * len(ti))
+        self._check(self._lib.fk_equal_time_moments(self._h, len(ti), ti.ctypes.data,
+                                                    _dptr(out)), "fk_equal_time_moments")
+        return out.view(np.complex128).reshape(len(ti), 3).T.copy()
 
     def impurity_update(self):
         d = ctypes.c_double()

@@ -79,6 +79,14 @@ def test_create_rejects_averaged_rule_beyond_150_points(lib):
     assert e.value.status == lib.FK_EINVAL
 
 
+def test_create_rejects_contour_beyond_5120_points(lib):
+    """N_c = 2 * 2550 + 22 = 5122 exceeds the inversion's largest matrix
+    (5120); the check runs before any device call."""
+    with pytest.raises(lib.FkError) as e:
+        lib.Context(-5, 250, 0.1, 0.1, 2.2, 0.5, 1.0)
+    assert e.value.status == lib.FK_EINVAL
+
+
 def _gauss_jordan_block(x, cols, candidates):
     """In-place Gauss-Jordan elimination of the columns `cols` of x with partial
     pivoting among `candidates`; returns the pivot rows in pivot order."""

@@ -664,3 +664,105 @@ def test_neville_extrapolation_is_exact_for_polynomials():
     # a cubic through three points is not reproduced (degree too high)
     f = [h ** 3 for h in hs]
     assert abs(extrapolate.to_zero(hs, f)) > 1e-4
+
+
+# ------------------------------------------------- nonequilibrium DOS, moments
+def _free_local_green(t_min, t_max, dt, dtau, beta, mu, n_eps):
+    """G_loc = sum_k rho_k G0_k at U = 0, E = 0 (Sigma = 0, so G_k = G0_k)."""
+    z, w = contour.points(t_min, t_max, dt, dtau, beta)
+    n_t = contour.sizes(t_min, t_max, dt, dtau, beta)[0]
+    x, wa = quadrature.hermite_rule(n_eps)
+    g = np.zeros((len(z), len(z)), dtype=np.complex128)
+    for a in range(n_eps):
+        g += wa[a] * green.g0_matrix(z, n_t, 0.0, mu, beta, x[a], 0.0)
+    return g, n_t
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.5])
+def test_dos_of_free_equilibrium_lattice_is_the_gaussian(mu):
+    """Sec. II, eqs. (gr_omega), (dos_def): without interaction and field the
+    local G^R(t, t') = -i int rho(e) e^{-i (e - mu)(t - t')} de, so the DOS at any
+    average time is the Gaussian DOS of eq. (joint_dos) shifted to w = e - mu:
+    rho(T, w) = exp(-(w + mu)^2) / sqrt(pi).  The window (t_rel <= 12,
+    exp(-36)) and the trapezoid aliasing (period 2 pi / h = 31) are negligible;
+    the 80-point rule integrates e^{-i e t} to ~1e-15 for t <= 12 (40 points
+    would leave 4e-5 at t = 12)."""
+    from oracle import dos
+    g, n_t = _free_local_green(0.0, 12.0, 0.1, 0.1, 1.0, mu, 80)
+    w = np.linspace(-3.0, 3.0, 61)
+    rho = dos.wigner_dos(g, n_t, 0.1, [60], w)[0]
+    assert np.max(np.abs(rho - np.exp(-(w + mu) ** 2) / math.sqrt(math.pi))) < 1e-9
+
+
+def test_dos_integrates_to_the_zeroth_moment():
+    """The w-integral of rho(T, w) over one period of the discrete transform
+    (2 pi / h, h = 2 dt) keeps only the t_rel = 0 term: it equals
+    -Im G^R(T, T) for any matrix (sum rule of the zeroth moment, Sec. II)."""
+    from oracle import dos
+    rng = np.random.default_rng(41)
+    n_t, n_tau, dt = 20, 4, 0.15
+    n_c = 2 * n_t + n_tau
+    g = rng.standard_normal((n_c, n_c)) + 1j * rng.standard_normal((n_c, n_c))
+    h = 2 * dt
+    m = 64                                       # > 2 * max window
+    w = -np.pi / h + (2 * np.pi / h) * np.arange(m) / m
+    for i in (0, 3, 9, 10, 19):
+        rho = dos.wigner_dos(g, n_t, dt, [i], w)[0]
+        integral = rho.sum() * (2 * np.pi / h) / m
+        m0 = g[2 * n_t - i, i] - g[i, 2 * n_t - i]
+        assert abs(integral + m0.imag) < 1e-12
+
+
+def test_dos_of_one_level_peaks_at_its_energy():
+    """A single level: G^R(t, t') = -i e^{-i e0 (t - t')}.  The truncated
+    transform is the trapezoid sum of a geometric series; it peaks at w = e0
+    (the sign of the exponent of eq. gr_omega) with height (h / pi) D
+    (D + 1 window points, end weights 1/2)."""
+    from oracle import dos
+    n_t, n_tau, dt, e0 = 41, 2, 0.1, 0.8
+    n_c = 2 * n_t + n_tau
+    t = np.arange(n_t) * dt
+    g = np.zeros((n_c, n_c), dtype=np.complex128)
+    for a in range(n_t):
+        for b in range(n_t):
+            g[2 * n_t - a, b] = -1j * np.exp(-1j * e0 * (t[a] - t[b]))
+    w = np.linspace(-2.0, 3.0, 501)
+    rho = dos.wigner_dos(g, n_t, dt, [20], w)[0]
+    assert abs(w[np.argmax(rho)] - e0) < 1e-12
+    h, dmax = 2 * dt, 20
+    assert abs(rho.max() - h / np.pi * dmax) < 1e-12
+
+
+def test_moments_exact_for_low_degree_polynomials():
+    """Sec. II moments: mu0 = i f(0), mu1 = -f'(0), mu2 = -i f''(0) with
+    f(s) = G^R(T + s/2, T - s/2).  The one-sided differences are exact for
+    f(s) = c0 + c1 s + c2 s^2 (first derivative) and for cubics (second)."""
+    from oracle import dos
+    n_t, n_tau, dt = 16, 3, 0.05
+    n_c = 2 * n_t + n_tau
+    t = np.arange(n_t) * dt
+    c0, c1, c2, c3 = 0.3 - 1.1j, -0.7 + 0.2j, 0.45 + 0.9j, -0.35 + 0.6j
+    for cubic in (0.0, c3):
+        g = np.zeros((n_c, n_c), dtype=np.complex128)
+        for a in range(n_t):
+            for b in range(a + 1):
+                s = t[a] - t[b]
+                g[2 * n_t - a, b] = c0 + c1 * s + c2 * s * s + cubic * s ** 3
+        mu = dos.moments(g, n_t, dt, [3, 7, n_t - 4])
+        assert np.max(np.abs(mu[0] - 1j * c0)) < 1e-13
+        assert np.max(np.abs(mu[2] - (-1j) * 2 * c2)) < 1e-9
+        if cubic == 0.0:
+            assert np.max(np.abs(mu[1] + c1)) < 1e-11
+
+
+def test_moments_of_free_equilibrium_lattice():
+    """Without interaction and field, mu0 = 1, mu1 = <e - mu> = -mu and
+    mu2 = <(e - mu)^2> = 1/2 + mu^2 (Gaussian DOS); the differences are
+    second-order accurate, error below 1e-3 at h = 0.02."""
+    from oracle import dos
+    mu_c = 0.3
+    g, n_t = _free_local_green(0.0, 0.4, 0.01, 0.1, 1.0, mu_c, 30)
+    mu = dos.moments(g, n_t, 0.01, [10, 20])
+    assert np.max(np.abs(mu[0] - 1.0)) < 1e-12
+    assert np.max(np.abs(mu[1] + mu_c)) < 1e-3
+    assert np.max(np.abs(mu[2] - (0.5 + mu_c ** 2))) < 1e-3
