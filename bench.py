@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--U", type=float, default=1.0)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "long"])
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--converge", action="store_true")
@@ -145,7 +145,12 @@ def main():
         sweep_bench(args)
         return
     stream = torch.cuda.current_stream()
-    w = configs.c2(args.U) if args.workload == "c2" else configs.C1
+    w = {"c2": lambda: configs.c2(args.U), "c1": lambda: configs.C1,
+         "long": lambda: configs.long_contour(args.U)}[args.workload]()
+    if args.workload == "long":
+        # the long contour is measured per lattice step and impurity update;
+        # the mixed and convergence blocks belong to the N_c = 1800 workload
+        args.no_mixed = args.no_converge = True
     ctx = fkdmft.Context(stream=stream, **w.kwargs())
     tuning = None
     if args.batch:
@@ -204,7 +209,8 @@ def main():
                if (kname == PROFILED_TRAFFIC["kernel"] and w.name.startswith("C2")
                    and tuned["batch"] == PROFILED_TRAFFIC["batch"]) else None)
     out = {
-        "metric": "sec/DMFT iteration at N_c=1800, FP64 vs mixed @1e-8; iters to converge",
+        "metric": ("sec/DMFT iteration at N_c=1800, FP64 vs mixed @1e-8; iters to converge"
+                   if args.workload == "c2" else f"sec/DMFT iteration at N_c={n}"),
         "value": sec,
         "unit": "s/iteration",
         "n_gpus": 1,
@@ -298,7 +304,9 @@ def main():
         out["converge"] = conv
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(w)
+        # a sample of about 10-30 s of host work: 48 points at N_c = 1800,
+        # proportionally fewer for larger matrices
+        out["cpu_baseline"] = cpu_baseline(w, n_sample=max(2, int(48 * (1800.0 / n) ** 3)))
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -49,6 +49,12 @@ def c2(U=1.0):
     return Workload(f"C2_U{U}", -10.0, 30.0, 0.05, 0.05, 10.0, U, 1.0, 55, 55)
 
 
+def long_contour(U=1.0, E=1.0):
+    """The paper's long runs (Figs. 7-9): t in [-5, 195], dt = dtau = 0.1,
+    beta = 10, N_c = 4100, here with the C2 quadrature (55 x 55 points)."""
+    return Workload(f"LONG_U{U}_E{E}", -5.0, 195.0, 0.1, 0.1, 10.0, U, E, 55, 55)
+
+
 C2_U = (0.5, 1.0, 1.5, 2.0)
 C2_TOL = 1e-8
 
