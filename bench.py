@@ -127,7 +127,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
-    ap.add_argument("--tune-bytes", type=float, default=48 * 2 ** 30)
+    ap.add_argument("--tune-bytes", type=float, default=0.0,
+                    help="autotuner byte budget (default 48 GiB, 96 GiB for the long contour)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not "
@@ -151,6 +152,8 @@ def main():
         # the long contour is measured per lattice step and impurity update;
         # the mixed and convergence blocks belong to the N_c = 1800 workload
         args.no_mixed = args.no_converge = True
+    if not args.tune_bytes:
+        args.tune_bytes = (96 if args.workload == "long" else 48) * 2.0 ** 30
     ctx = fkdmft.Context(stream=stream, **w.kwargs())
     tuning = None
     if args.batch:

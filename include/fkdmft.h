@@ -236,8 +236,9 @@ typedef struct {
 } fk_tuning;
 
 /* Time candidate schedules on this context's own point matrices (current
- * Sigma): every tile height x batch sizes up to max_bytes of device memory x
- * look-ahead on/off; each candidate inverts one batch once for warm-up and
+ * Sigma): every tile height x batch sizes up to max_bytes of device memory (the
+ * budget, its half and quarter, and one to three times the device's compute
+ * unit count) x look-ahead on/off; each candidate inverts one batch once for warm-up and
  * once timed, the estimate scales to all points.  Applies and returns the
  * fastest.  keep = 0 frees the inversion buffers afterwards. */
 fk_status fk_autotune(fk_ctx* ctx, double max_bytes, int keep, fk_tuning* best);

@@ -1069,10 +1069,22 @@ extern "C" fk_status fk_autotune(fk_ctx* c, double max_bytes, int keep,
   const double mb = matrix_bytes(c);
   int cap_max = (int)std::min<double>(c->npts, std::floor(max_bytes / mb));
   if (cap_max < 1) return set_err(c, FK_ENOMEM, "max_bytes below one matrix");
+  // the byte budget and its halves and quarters, and whole multiples of the
+  // compute-unit count (the panel runs one workgroup per matrix, so a batch
+  // that fills the CUs exactly avoids a partial round of panel workgroups)
   std::vector<int> caps;
   for (int d : {4, 2, 1}) {
     const int b = std::max(1, cap_max / d);
     if (std::find(caps.begin(), caps.end(), b) == caps.end()) caps.push_back(b);
+  }
+  int dev = 0, ncu = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  for (int k = 1; k <= 3 && ncu > 0; ++k) {
+    const int b = k * ncu;
+    if (b <= cap_max && b < c->npts &&
+        std::find(caps.begin(), caps.end(), b) == caps.end())
+      caps.push_back(b);
   }
   const int n = c->ci.n_c;
   HIPCHK(c, launch_sigma_weight(c->d_sigma, c->d_w, c->d_sigt, n, c->st));

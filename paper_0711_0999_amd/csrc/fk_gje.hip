@@ -219,10 +219,12 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
                              unsigned char* smem) {
   static_assert(PW % IB == 0 && PW <= kNB, "panel width");
   cplx<T>* Bo = reinterpret_cast<cplx<T>*>(smem);   // [IB][PW]
-  cplx<T>* prow = Bo + IB * PW;                     // [IB]
-  T* redv = reinterpret_cast<T*>(prow + IB);        // [kPW]
-  int* redi = reinterpret_cast<int*>(redv + kPW);    // [kPW]
-  int* pvt = redi + kPW;                             // [IB]
+  // pivot row and the waves' pivot candidates, double-buffered by column
+  // parity so one column's reads never meet the next column's writes
+  cplx<T>* prow2 = Bo + IB * PW;                     // [2][IB]
+  T* redv2 = reinterpret_cast<T*>(prow2 + 2 * IB);   // [2][kPW]
+  int* redi2 = reinterpret_cast<int*>(redv2 + 2 * kPW);  // [2][kPW]
+  int* pvt = redi2 + 2 * kPW;                        // [IB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cw = min(PW, n - c0);
   const T inf_key = big_value<T>();
@@ -257,6 +259,9 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
 #pragma unroll
     for (int l = 0; l < IB; ++l) {
       if (l >= iw) break;
+      cplx<T>* prow = prow2 + (l & 1) * IB;
+      T* redv = redv2 + (l & 1) * kPW;
+      int* redi = redi2 + (l & 1) * kPW;
       // ---- pivot search: largest |re|+|im| among unpivoted rows (bidx is
       // a list index)
       T best = T(-1);
@@ -348,7 +353,6 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
           v[i][l].im = -nm.im;
         }
       }
-      __syncthreads();  // redv / prow reused by the next column
     }
     // ---- write the eliminated block back; old pivot rows of the other columns
 #pragma unroll
@@ -429,11 +433,11 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
 // list of the rows the block works on.
 template <typename T> __host__ __device__ constexpr size_t panel_body_bytes() {
   return ((sizeof(cplx<T>) * (size_t)(kNB + kTile) * kPitch >
-                   sizeof(cplx<T>) * (kIB * kNB + kIB) + kPW * sizeof(T) +
-                       kPW * sizeof(int) + kIB * sizeof(int)
+                   sizeof(cplx<T>) * (kIB * kNB + 2 * kIB) + 2 * kPW * sizeof(T) +
+                       2 * kPW * sizeof(int) + kIB * sizeof(int)
                ? sizeof(cplx<T>) * (size_t)(kNB + kTile) * kPitch
-               : sizeof(cplx<T>) * (kIB * kNB + kIB) + kPW * sizeof(T) +
-                     kPW * sizeof(int) + kIB * sizeof(int)) + 15) / 16 * 16;
+               : sizeof(cplx<T>) * (kIB * kNB + 2 * kIB) + 2 * kPW * sizeof(T) +
+                     2 * kPW * sizeof(int) + kIB * sizeof(int)) + 15) / 16 * 16;
 }
 template <typename T> static size_t panel_lds_bytes(int rpt) {
   return panel_body_bytes<T>() + sizeof(int) * (size_t)rpt * kPanelThreads;
@@ -602,15 +606,16 @@ __global__ __launch_bounds__(512, 1) void k_fix(
       Bsh[buf][k * BP + c] = v;
     }
   };
-  v4 cr[2][2], ci[2][2];
+  v4 p1[2][2], p2[2][2], p3[2][2];   // three-product form, as k_update
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
     for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        cr[ii][jj][v] = T(0);
-        ci[ii][jj][v] = T(0);
+        p1[ii][jj][v] = T(0);
+        p2[ii][jj][v] = T(0);
+        p3[ii][jj][v] = T(0);
       }
   load(0);
   stash(0, 0);
@@ -623,28 +628,28 @@ __global__ __launch_bounds__(512, 1) void k_fix(
     const cplx<T>* bs = Bsh[buf];
 #pragma unroll
     for (int k = 0; k < kKC; k += 4) {
-      T ar[2], ai[2], an[2], br[2], bi[2];
+      T ar[2], ai[2], as_[2], br[2], bi[2], bs_[2];
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii) {
         const cplx<T> a = as[(32 * wr + 16 * ii + li) * AP + k + lk];
         ar[ii] = a.re;
         ai[ii] = a.im;
-        an[ii] = -a.im;
+        as_[ii] = a.re + a.im;
       }
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj) {
         const cplx<T> b = bs[(k + lk) * BP + 32 * wc + 16 * jj + li];
         br[jj] = b.re;
         bi[jj] = b.im;
+        bs_[jj] = b.re + b.im;
       }
 #pragma unroll
       for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
-          cr[ii][jj] = Mfma<T>::run(ar[ii], br[jj], cr[ii][jj]);
-          ci[ii][jj] = Mfma<T>::run(ar[ii], bi[jj], ci[ii][jj]);
-          cr[ii][jj] = Mfma<T>::run(an[ii], bi[jj], cr[ii][jj]);
-          ci[ii][jj] = Mfma<T>::run(ai[ii], br[jj], ci[ii][jj]);
+          p1[ii][jj] = Mfma<T>::run(ar[ii], br[jj], p1[ii][jj]);
+          p2[ii][jj] = Mfma<T>::run(ai[ii], bi[jj], p2[ii][jj]);
+          p3[ii][jj] = Mfma<T>::run(as_[ii], bs_[jj], p3[ii][jj]);
         }
     }
     if (more) stash((kc + 1) * kKC, buf ^ 1);
@@ -661,8 +666,9 @@ __global__ __launch_bounds__(512, 1) void k_fix(
         const int col = 32 * wc + 16 * jj + li;
         if (col < wO) {
           cplx<T> c;
-          c.re = -cr[ii][jj][v];
-          c.im = -ci[ii][jj][v];
+          const T q1 = p1[ii][jj][v], q2 = p2[ii][jj][v];
+          c.re = q2 - q1;
+          c.im = (q1 + q2) - p3[ii][jj][v];
           xm[(size_t)r * ld + J0 + col] = c;
         }
       }

@@ -33,7 +33,9 @@ __global__ void k_unpermute(const cplx<TI>* __restrict__ x, size_t xstride,
 
 // C[m] = beta Cin[m] + A[m] B[m] for n x n complex128 matrices (leading
 // dimension n).  sA = 0 shares A across the batch.  64 x 64 tiles, 2 x 2 waves
-// of 32 x 32, K in double-buffered chunks of 16, f64 matrix cores.
+// of 32 x 32, K in double-buffered chunks of 16, f64 matrix cores, three real
+// products per complex one (Gauss: Re = P1 - P2, Im = P3 - P1 - P2 with
+// P1 = Re a Re b, P2 = Im a Im b, P3 = (Re a + Im a)(Re b + Im b)).
 constexpr int kGT = 64, kGK = 16;
 __global__ __launch_bounds__(256, 2) void k_bgemm(
     c64* __restrict__ C, const c64* __restrict__ Cin, double beta,
@@ -58,19 +60,16 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(
     const int r0 = tr * kGT, c0 = tc * kGT;
     const c64* am = A + sA * m;
     const c64* bm = B + ss * m;
-    v4d cr[2][2], ci[2][2];
+    v4d p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = min(r0 + 32 * wr + 16 * ii + lk + 4 * v, n - 1);
-          const int col = min(c0 + 32 * wc + 16 * jj + li, n - 1);
-          c64 c{0.0, 0.0};
-          if (beta != 0.0) c = Cin[ss * m + (size_t)row * n + col];
-          cr[ii][jj][v] = beta * c.re;
-          ci[ii][jj][v] = beta * c.im;
+          p1[ii][jj][v] = 0.0;
+          p2[ii][jj][v] = 0.0;
+          p3[ii][jj][v] = 0.0;
         }
     c64 pa[4], pb[4];
     auto load = [&](int kb) {
@@ -106,33 +105,28 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(
       if (more) load((kc + 1) * kGK);
 #pragma unroll
       for (int k = 0; k < kGK; k += 4) {
-        double ar[2], ai[2], an[2], br[2], bi[2];
+        double ar[2], ai[2], as_[2], br[2], bi[2], bs_[2];
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii) {
           const c64 a = As[buf][(32 * wr + 16 * ii + li) * AP + k + lk];
           ar[ii] = a.re;
           ai[ii] = a.im;
-          an[ii] = -a.im;
+          as_[ii] = a.re + a.im;
         }
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
           const c64 b = Bs[buf][(k + lk) * BP + 32 * wc + 16 * jj + li];
           br[jj] = b.re;
           bi[jj] = b.im;
+          bs_[jj] = b.re + b.im;
         }
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj) {
-            cr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ii], br[jj], cr[ii][jj], 0, 0, 0);
-            ci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ii], bi[jj], ci[ii][jj], 0, 0, 0);
-          }
-#pragma unroll
-        for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-          for (int jj = 0; jj < 2; ++jj) {
-            cr[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[ii], bi[jj], cr[ii][jj], 0, 0, 0);
-            ci[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[ii], br[jj], ci[ii][jj], 0, 0, 0);
+            p1[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ii], br[jj], p1[ii][jj], 0, 0, 0);
+            p2[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[ii], bi[jj], p2[ii][jj], 0, 0, 0);
+            p3[ii][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(as_[ii], bs_[jj], p3[ii][jj], 0, 0, 0);
           }
       }
       if (more) stash(buf ^ 1, (kc + 1) * kGK);
@@ -146,8 +140,13 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(
         for (int v = 0; v < 4; ++v) {
           const int row = r0 + 32 * wr + 16 * ii + lk + 4 * v;  // f64 layout
           const int col = c0 + 32 * wc + 16 * jj + li;
-          if (row < n && col < n)
-            C[ss * m + (size_t)row * n + col] = c64{cr[ii][jj][v], ci[ii][jj][v]};
+          if (row < n && col < n) {
+            const size_t e = ss * m + (size_t)row * n + col;
+            c64 c{0.0, 0.0};
+            if (beta != 0.0) c = Cin[e];
+            const double q1 = p1[ii][jj][v], q2 = p2[ii][jj][v];
+            C[e] = c64{(q1 - q2) + beta * c.re, ((p3[ii][jj][v] - q1) - q2) + beta * c.im};
+          }
         }
   }
 }
