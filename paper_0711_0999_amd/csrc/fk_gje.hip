@@ -228,7 +228,8 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cw = min(PW, n - c0);
   const T inf_key = big_value<T>();
-  constexpr int kGB = GroupBatch<T>::value * 8 / IB;
+  constexpr int kGBr = GroupBatch<T>::value * 8 / IB, kGBo = PW / IB - 1;
+  constexpr int kGB = (kGBr < kGBo ? kGBr : kGBo) > 0 ? (kGBr < kGBo ? kGBr : kGBo) : 1;
 
   bool pvd[RPT];
   int rr[RPT];
@@ -330,25 +331,31 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       cplx<T> inv;
       inv.re = pv.re / den;
       inv.im = -pv.im / den;
-      cplx<T> ps[IB];
+      // column by column of the register block (the scaled pivot row entry
+      // is formed from LDS as it is used, which keeps registers for v)
+      cplx<T> mi[RPT];
 #pragma unroll
-      for (int l2 = 0; l2 < IB; ++l2) ps[l2] = cmul(prow[l2], inv);
-      ps[l] = inv;
+      for (int i = 0; i < RPT; ++i) mi[i] = v[i][l];
+#pragma unroll
+      for (int l2 = 0; l2 < IB; ++l2) {
+        if (l2 == l) continue;
+        const cplx<T> q = cmul(prow[l2], inv);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          if (tid + i * kPanelThreads == pe) {
+            v[i][l2] = q;
+          } else {
+            v[i][l2].re -= mi[i].re * q.re - mi[i].im * q.im;
+            v[i][l2].im -= mi[i].re * q.im + mi[i].im * q.re;
+          }
+        }
+      }
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int e = tid + i * kPanelThreads;
-        if (e == pe) {
-#pragma unroll
-          for (int l2 = 0; l2 < IB; ++l2) v[i][l2] = ps[l2];
+        if (tid + i * kPanelThreads == pe) {
+          v[i][l] = inv;
         } else {
-          const cplx<T> m = v[i][l];
-#pragma unroll
-          for (int l2 = 0; l2 < IB; ++l2)
-            if (l2 != l) {
-              v[i][l2].re -= m.re * ps[l2].re - m.im * ps[l2].im;
-              v[i][l2].im -= m.re * ps[l2].im + m.im * ps[l2].re;
-            }
-          const cplx<T> nm = cmul(m, inv);
+          const cplx<T> nm = cmul(mi[i], inv);
           v[i][l].re = -nm.re;
           v[i][l].im = -nm.im;
         }
