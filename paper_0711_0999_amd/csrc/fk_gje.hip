@@ -231,13 +231,14 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
   constexpr int kGBr = GroupBatch<T>::value * 8 / IB, kGBo = PW / IB - 1;
   constexpr int kGB = (kGBr < kGBo ? kGBr : kGBo) > 0 ? (kGBr < kGBo ? kGBr : kGBo) : 1;
 
-  bool pvd[RPT];
-  int rr[RPT];
+  // bit i: list entry tid + i kPanelThreads is pivoted (or absent); row ids
+  // are re-read from the LDS list where needed (registers go to v)
+  unsigned pvd = 0u;
+  static_assert(RPT <= 32, "pivot bits");
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int e = tid + i * kPanelThreads;
-    rr[i] = rows[min(e, m - 1)];
-    pvd[i] = (e < m) ? (rowcol[rr[i]] >= 0) : true;
+    if (!(e < m) || rowcol[rows[min(e, m - 1)]] >= 0) pvd |= 1u << i;
   }
   const int ngroups = (cw + IB - 1) / IB;
 
@@ -248,7 +249,8 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
     for (int i = 0; i < RPT; ++i) {
 #pragma unroll
       for (int l = 0; l < IB; ++l)
-        v[i][l] = x[(size_t)rr[i] * ld + c0 + b0 + min(l, iw - 1)];
+        v[i][l] = x[(size_t)rows[min(tid + i * kPanelThreads, m - 1)] * ld + c0 + b0 +
+                    min(l, iw - 1)];
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
@@ -270,7 +272,7 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int e = tid + i * kPanelThreads;
-        if (e < m && !pvd[i]) {
+        if (e < m && !((pvd >> i) & 1u)) {
           T a = fabs(v[i][l].re) + fabs(v[i][l].im);
           if (!(a <= inf_key)) a = inf_key;  // NaN / Inf win and get flagged
           if (a > best || (a == best && e < bidx)) {
@@ -318,7 +320,7 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
           if (ii == i) {
 #pragma unroll
             for (int l2 = 0; l2 < IB; ++l2) prow[l2] = v[ii][l2];
-            pvd[ii] = true;
+            pvd |= 1u << ii;
           }
         piv[col] = p;
         rowcol[p] = col;
@@ -331,8 +333,9 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       cplx<T> inv;
       inv.re = pv.re / den;
       inv.im = -pv.im / den;
-      // column by column of the register block (the scaled pivot row entry
-      // is formed from LDS as it is used, which keeps registers for v)
+      // column by column of the register block: the scaled pivot row entry is
+      // formed from LDS as it is used (RPT multipliers in registers instead of
+      // IB scaled entries; fewer spills in both panel shapes)
       cplx<T> mi[RPT];
 #pragma unroll
       for (int i = 0; i < RPT; ++i) mi[i] = v[i][l];
@@ -368,7 +371,7 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       if (e < m) {
 #pragma unroll
         for (int l = 0; l < IB; ++l)
-          if (l < iw) x[(size_t)rr[i] * ld + c0 + b0 + l] = v[i][l];
+          if (l < iw) x[(size_t)rows[e] * ld + c0 + b0 + l] = v[i][l];
       }
     }
     for (int e = tid; e < IB * PW; e += kPanelThreads) {
