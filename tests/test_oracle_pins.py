@@ -766,3 +766,61 @@ def test_moments_of_free_equilibrium_lattice():
     assert np.max(np.abs(mu[0] - 1.0)) < 1e-12
     assert np.max(np.abs(mu[1] + mu_c)) < 1e-3
     assert np.max(np.abs(mu[2] - (0.5 + mu_c ** 2))) < 1e-3
+
+
+# ------------------------------------------ equilibrium Matsubara-axis solver
+def test_matsubara_free_g_tau_matches_real_energy_quadrature():
+    """U = 0: the Matsubara sum with the 1/(i w_n) tail subtracted equals
+    G(tau) = -int rho(e) (1 - f(e)) e^{-e tau} de, evaluated by adaptive
+    quadrature over the Gaussian DOS (eq. joint_dos)."""
+    from scipy.integrate import quad
+    from oracle import matsubara
+    beta = 4.0
+    _, giw, _, _ = matsubara.solve(0.0, beta, 40000)
+    for tau in (0.1, 1.0, 2.0, 3.7):
+        f = lambda e: -np.exp(-e * e) / math.sqrt(math.pi) * np.exp(-e * tau) / (1.0 + np.exp(-beta * e))
+        ref = quad(f, -12.0, 12.0, epsabs=1e-13, limit=200)[0]
+        assert abs(matsubara.g_tau(beta, giw, [tau])[0] - ref) < 1e-8
+
+
+def test_matsubara_self_energy_tail_is_second_moment():
+    """Half filling, symmetric convention: Sigma = U^2/(4 G0^-1) exactly, so
+    i w Sigma(i w) -> U^2/4 at large frequency (the U^2/4 of the second
+    moment, Sec. II)."""
+    from oracle import matsubara
+    for u in (0.5, 1.0, 2.0):
+        z, _, sig, _ = matsubara.solve(u, 4.0, 3000)
+        assert abs((z[-1] * sig[-1]).real - u * u / 4.0) < 1e-4 * max(1.0, u * u)
+
+
+def test_metal_insulator_transition_at_sqrt_two():
+    """Sec. III: the equilibrium model is a metal below U = sqrt(2) and an
+    insulator above: rho(0) = 1/sqrt(pi) at U = 0, positive and decreasing
+    up to sqrt(2), zero (to the O(eta) of z = i eta) beyond."""
+    from oracle import matsubara
+    assert abs(matsubara.dos_at_zero(0.0) - 1.0 / math.sqrt(math.pi)) < 1e-8
+    vals = [matsubara.dos_at_zero(u) for u in (0.5, 1.0, 1.3, 1.41)]
+    assert all(a > b for a, b in zip(vals, vals[1:])) and vals[-1] > 0.01
+    for u in (1.42, 1.5, 1.6):
+        assert matsubara.dos_at_zero(u) < 1e-5
+
+
+def test_contour_imaginary_branch_matches_matsubara_solver():
+    """The contour oracle at E = 0 (the equilibrium of Sec. II): its
+    imaginary-branch block is i G(tau - tau') of the independent Matsubara
+    solver, to first order in the step (errors 6e-3, 2.6e-3, 1.2e-3 at
+    dtau = 0.2, 0.1, 0.05; U = 1, beta = 4)."""
+    from oracle import matsubara
+    beta, u = 4.0, 1.0
+    _, giw, _, _ = matsubara.solve(u, beta, 40000)
+    errs = []
+    for dtau in (0.2, 0.1, 0.05):
+        p = dmft.Problem(t_min=0.0, t_max=dtau, dt=dtau, dtau=dtau, beta=beta, u=u,
+                         e_field=0.0, n_eps=30, n_ebar=1)
+        ro = dmft.run(p, 300, tol=1e-13)
+        n_t = ro["n_t"]
+        k = np.arange(int(round(beta / dtau)))
+        g_contour = -1j * ro["gloc"][2 * n_t + k, 2 * n_t]
+        errs.append(np.max(np.abs(g_contour - matsubara.g_tau(beta, giw, k * dtau))))
+    assert errs[-1] < 2e-3
+    assert 0.35 < errs[1] / errs[0] < 0.6 and 0.35 < errs[2] / errs[1] < 0.6
