@@ -30,6 +30,8 @@
 #include <float.h>
 #include <limits.h>
 
+#include <atomic>
+
 namespace fk {
 
 // 16x16x4 matrix-core products.  Operands: lane l holds A[l%16][l/16] and
@@ -885,9 +887,15 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
 template <typename T>
 hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
                      int nmat, int nmax, int S, int* status, hipStream_t st) {
-  static bool attr_set = false;
+  // the dynamic-LDS limit is a per-device attribute of each kernel: set once
+  // per device (outside any graph capture: the first call on a device may
+  // pass nmat = 0 for just this)
+  static std::atomic<unsigned> attr_set{0u};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  const unsigned bit = dev < 32 ? (1u << dev) : 0u;
   const size_t lds_s = panel_lds_bytes<T>(kRPTs), lds_l = panel_lds_bytes<T>(kRPTl);
-  if (!attr_set) {
+  if (!bit || !(attr_set.load() & bit)) {
     hipError_t e = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&k_outer_panel<T, kRPTs, kIBs>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
@@ -896,7 +904,7 @@ hipError_t gje_panel(cplx<T>* x, int* piv, int* rowcol, const MatDesc* d,
           reinterpret_cast<const void*>(&k_outer_panel<T, kRPTl, kIBl>),
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_l);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    attr_set.fetch_or(bit);
   }
   if (nmat <= 0) return hipSuccess;
   if (nmax > kMaxN) return hipErrorInvalidValue;
