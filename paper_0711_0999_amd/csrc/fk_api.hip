@@ -1092,7 +1092,8 @@ extern "C" fk_status fk_autotune(fk_ctx* c, double max_bytes, int keep,
   int trials = 0;
   fk_status s;
   for (int variant : {0, 1})
-    for (int cap : caps)
+    for (int cap : caps) {
+      double est_plain = std::numeric_limits<double>::infinity();
       for (int la : {0, 1}) {
         c->variant = variant;
         c->want_batch = cap;
@@ -1116,7 +1117,11 @@ extern "C" fk_status fk_autotune(fk_ctx* c, double max_bytes, int keep,
         const double est = ms / nmat * c->npts *
                            (double)((c->npts + nmat - 1) / nmat) * nmat / c->npts;
         ++trials;
-        if (est < bestt.est_step_ms) {
+        if (!la) est_plain = est;
+        // the look-ahead stream counts only when it wins clearly: one batch
+        // timed once cannot resolve smaller differences
+        const bool counts = !la || est < 0.98 * est_plain;
+        if (counts && est < bestt.est_step_ms) {
           bestt.tile_rows = variant ? 128 : 64;
           bestt.batch = nmat;
           bestt.lookahead = la;
@@ -1124,6 +1129,7 @@ extern "C" fk_status fk_autotune(fk_ctx* c, double max_bytes, int keep,
           bestt.est_step_ms = est;
         }
       }
+    }
   bestt.trials = trials;
   batch_free(c->b64);
   if ((s = fk_set_tuning(c, &bestt)) != FK_OK) return s;
