@@ -92,7 +92,9 @@ const char* fk_status_string(fk_status s);
 /* ---- context ------------------------------------------------------------- */
 
 /* Create a context on the current HIP device.  hip_stream is a hipStream_t
- * (NULL: the library creates its own default-priority stream).  Sigma starts
+ * (NULL: the library creates its own default-priority stream).  The contour
+ * size N_c = 2 N_t + N_tau must lie in [3, 5120] (the largest matrix the
+ * inversion takes), else FK_EINVAL before any device call.  Sigma starts
  * at zero.  Device memory for the batched inversion is sized by
  * FKDMFT_BATCH_BYTES (environment, bytes; default 24 GiB) or fk_set_batch. */
 fk_status fk_create(const fk_contour* c, const fk_model* m, void* hip_stream,
