@@ -82,3 +82,30 @@ def test_retirement_and_recapture(lib):
                 assert relerr(b.instance(i).get_gloc(), c.get_gloc()) < 1e-11
         assert len(set(r["iters"])) > 1
         assert b.timings()["captures"] >= 2
+
+
+def test_batch_mixing_small_and_long_contours(lib):
+    """An uneven batch whose largest matrix exceeds 2048 rows runs every matrix
+    with the panel's large shape (ten rows per thread, four columns per
+    register block): N_c = 73 and 2300 in one sweep, replayed from the graph,
+    against single-instance runs (where the N_c = 73 instance takes the small
+    shape) and the oracle."""
+    print("case: batch of N_c = 73 and 2300, 2 sweeps, graph", flush=True)
+    inst = [INSTANCES[0],
+            dict(t_min=-5.0, t_max=50.0, dt=0.05, dtau=0.1, beta=10.0, U=1.0, E=1.0,
+                 n_eps=2, n_ebar=2)]
+    with lib.Batch(inst) as b:
+        r = b.iterate(2, tol=0.0, use_graph=True)
+        assert list(r["iters"]) == [2, 2]
+        for i, kw in enumerate(inst):
+            with lib.Context(**kw) as c:
+                c.iterate(2, tol=0.0)
+                v = b.instance(i)
+                assert relerr(v.get_gloc(), c.get_gloc()) < 1e-10
+                assert relerr(v.get_sigma(), c.get_sigma()) < 1e-9
+        kw = inst[0]
+        ro = dmft.run(dmft.Problem(t_min=kw["t_min"], t_max=kw["t_max"], dt=kw["dt"],
+                                   dtau=kw["dtau"], beta=kw["beta"], u=kw["U"],
+                                   e_field=kw["E"], n_eps=kw["n_eps"],
+                                   n_ebar=kw["n_ebar"]), 2)
+        assert relerr(b.instance(0).get_gloc(), ro["gloc"]) < 1e-10
