@@ -87,32 +87,33 @@ hipError_t launch_ttab(const PointTables& tab, int k0, int nmat, int n,
   return hipGetLastError();
 }
 
+// One thread per column j of row i = blockIdx.y: the row of -Sigma~ is read
+// once and written to the matrices m = blockIdx.z, blockIdx.z + gridDim.z, ...
+// with i on the diagonal and the point's sub-diagonal / corner entry added.
 template <typename TO>
 __global__ void k_build(const c64* __restrict__ sigt,
                         const PointTables tab, int k0, int nmat,
                         cplx<TO>* __restrict__ xbuf, size_t mat_stride, int ld,
                         int n) {
-  const size_t per = (size_t)n * n;
-  const size_t total = per * nmat;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int m = (int)(e / per);
-    const size_t f = e - (size_t)m * per;
-    const int i = (int)(f / n), j = (int)(f - (f / n) * n);
-    const c64 s = sigt[f];
-    c64 a;
-    a.re = -s.re;
-    a.im = -s.im;
-    if (j == i) {
-      a.im += 1.0;
-    } else if (j == i - 1 || (i == 0 && j == n - 1)) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const c64 s = sigt[(size_t)i * n + j];
+  c64 a;
+  a.re = -s.re;
+  a.im = -s.im;
+  if (j == i) a.im += 1.0;
+  const bool sub = j != i && (j == i - 1 || (i == 0 && j == n - 1));
+  for (int m = blockIdx.z; m < nmat; m += gridDim.z) {
+    c64 v = a;
+    if (sub) {
       const c64 t = (j == i - 1) ? t_sub(tab, k0 + m, i) : t_corner(tab, k0 + m);
-      a.re += t.re;
-      a.im += t.im;
+      v.re += t.re;
+      v.im += t.im;
     }
     cplx<TO> o;
-    o.re = (TO)a.re;
-    o.im = (TO)a.im;
+    o.re = (TO)v.re;
+    o.im = (TO)v.im;
     xbuf[(size_t)m * mat_stride + (size_t)i * ld + j] = o;
   }
 }
@@ -413,9 +414,10 @@ template <typename TO>
 hipError_t launch_build(const c64* sigt, const PointTables& tab, int k0,
                         int nmat, cplx<TO>* xbuf, size_t mat_stride, int ld,
                         int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_build<TO>, dim3(grid_for((size_t)n * n * nmat, 256)),
-                     dim3(256), 0, st, sigt, tab, k0, nmat, xbuf, mat_stride,
-                     ld, n);
+  if (nmat <= 0) return hipSuccess;
+  const int gz = nmat < 16 ? nmat : 16;
+  hipLaunchKernelGGL(k_build<TO>, dim3((n + 255) / 256, n, gz), dim3(256), 0, st, sigt,
+                     tab, k0, nmat, xbuf, mat_stride, ld, n);
   return hipGetLastError();
 }
 
