@@ -137,3 +137,15 @@ def test_deferred_rows_block_identity():
     rowcol[done] = np.arange(n)
     inv = x[np.ix_(done, rowcol)]
     np.testing.assert_allclose(inv, np.linalg.inv(a), rtol=1e-10, atol=1e-12)
+
+
+def test_spectral_entry_points_reject_null_arguments(lib):
+    """fk_wigner_dos and fk_equal_time_moments check their arguments before
+    any device call: a NULL context or array, or empty sizes, give FK_EINVAL."""
+    L = lib.library()
+    ti = (ctypes.c_int * 1)(0)
+    om = (ctypes.c_double * 1)(0.0)
+    out = (ctypes.c_double * 6)()
+    assert L.fk_wigner_dos(None, 1, ti, 1, om, out) == lib.FK_EINVAL
+    assert L.fk_equal_time_moments(None, 1, ti, out) == lib.FK_EINVAL
+    assert L.fk_get_zeroth_moment(None, out) == lib.FK_EINVAL
