@@ -394,7 +394,7 @@ fk_status impurity(fk_ctx* c, double* dsig) {
   if (!c->have_gloc) return set_err(c, FK_ESTATE, "impurity update before a lattice step");
   const int n = c->ci.n_c;
   Batch<double>& b = c->imp;
-  if (!b.x) HIPCHK(c, batch_alloc(b, 2, n));
+  if (!b.x) HIPCHK(c, batch_alloc(b, 1, n));
   int launches = 0;
   fk_status s;
   HIPCHK(c, hipEventRecord(c->ev[4], c->st));
@@ -405,7 +405,11 @@ fk_status impurity(fk_ctx* c, double* dsig) {
   HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                   c->d_coef, 1, n, c->d_g0inv, 0, c->st));
   HIPCHK(c, launch_add_right_weighted(c->d_g0inv, c->d_sigma, c->d_w, n, c->st));
-  // G_imp = (1 - w1)(g0inv + d0 S)^-1 + w1 (g0inv + d1 S)^-1
+  // G_imp = (1 - w1) A0^-1 + w1 A1^-1 with A_m = g0inv + d_m S has the inverse
+  // A1 C^-1 A0, C = (1 - w1) A1 + w1 A0 = g0inv + d_c S, so that
+  //   Sigma_new W = g0inv - G_imp^-1 = -h S + w1 (1 - w1) (d0 - d1)^2 S C^-1 S,
+  // h = (1 - w1) d0 + w1 d1: one inversion instead of the pair and the
+  // inverse of their combination.
   double d0, d1;
   if (c->m.convention == 0) {
     d0 = 0.5 * c->m.U;
@@ -414,22 +418,17 @@ fk_status impurity(fk_ctx* c, double* dsig) {
     d0 = 0.0;
     d1 = -c->m.U;
   }
-  HIPCHK(c, launch_shifted_pair(c->d_g0inv, d0, d1, b.x, b.x + b.stride, b.ld, n,
-                                c->st));
-  HIPCHK(c, batch_invert<double>(b, 2, c->st, c->aux, &launches));
-  if ((s = check_status(c, b.status, 2, 0, "impurity resolvents")) != FK_OK) return s;
-  HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
-                                  c->d_coef + 1, 2, n, c->d_tmp, 0, c->st));
-  HIPCHK(c, hipMemcpyAsync(b.x, c->d_tmp, sizeof(c64) * (size_t)n * n,
-                           hipMemcpyDeviceToDevice, c->st));
+  const double w1 = c->m.w1;
+  const double dc = (1.0 - w1) * d1 + w1 * d0, h = (1.0 - w1) * d0 + w1 * d1;
+  const double gam = w1 * (1.0 - w1) * (d0 - d1) * (d0 - d1);
+  HIPCHK(c, launch_shifted_pair(c->d_g0inv, dc, dc, b.x, nullptr, b.ld, n, c->st));
   HIPCHK(c, batch_invert<double>(b, 1, c->st, c->aux, &launches));
-  if ((s = check_status(c, b.status, 1, 0, "inverse of G_imp")) != FK_OK) return s;
+  if ((s = check_status(c, b.status, 1, 0, "inverse of the combined resolvent")) != FK_OK)
+    return s;
   HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                   c->d_coef, 1, n, c->d_tmp, 0, c->st));
-  // Sigma <- (g0inv - G_imp^-1) W^-1
   HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
-  HIPCHK(c, launch_sigma_new(c->d_g0inv, c->d_tmp, c->d_w, c->d_sigma, n,
-                             c->d_key, c->st));
+  HIPCHK(c, launch_sigma_fk(c->d_tmp, c->d_w, c->d_sigma, n, h, gam, c->d_key, c->st));
   HIPCHK(c, hipEventRecord(c->ev[5], c->st));
   double mx = read_key(c, &s);
   if (s != FK_OK) return s;

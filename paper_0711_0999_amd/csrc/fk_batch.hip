@@ -29,11 +29,10 @@ struct InstDev {
   c64* sigma;
   const c64* w;
   c64* g0inv;
-  c64* tmp;
   int n;
   double d0, d1, w1;
-  long long s0, s1;  // element offsets of the two impurity slots
-  int i0, i1;        // int offsets of their pivot arrays
+  long long s0;      // element offset of the impurity slot
+  int i0;            // int offset of its pivot arrays
   int key;           // slot of this instance in the key array (2 per instance)
 };
 
@@ -42,12 +41,13 @@ __device__ inline c64 cmulw(c64 a, c64 b) {
 }
 
 // Stages of the Falicov-Kimball update in right-weighted form (A -> A W):
-//   0: slot0 = G_loc W
-//   1: g0inv = inv(slot0) + Sigma W
-//   2: slot0 = g0inv + d0 S, slot1 = g0inv + d1 S  (S the point-split delta)
-//   3: tmp = (1 - w1) inv(slot0) + w1 inv(slot1)
-//   4: slot0 = tmp
-//   5: Sigma <- (g0inv - inv(slot0)) W^-1, key = max |Sigma change|
+//   0: slot = G_loc W
+//   1: g0inv = inv(slot) + Sigma W
+//   2: slot = C = g0inv + d_c S  (S the point-split delta, d_c = (1 - w1) d1 + w1 d0)
+//   3: Sigma <- (-h S + w1 (1 - w1) (d0 - d1)^2 S inv(C) S) W^-1, key = max
+//      |Sigma change|  (h = (1 - w1) d0 + w1 d1: the inverse of the impurity
+//      Green's function (1 - w1)(g0inv + d0 S)^-1 + w1 (g0inv + d1 S)^-1 is
+//      (g0inv + d1 S) inv(C) (g0inv + d0 S), one inversion instead of three)
 __global__ void k_imp_stage(const InstDev* __restrict__ inst, int stage,
                             c64* __restrict__ ximp, const int* __restrict__ piv,
                             const int* __restrict__ rc,
@@ -68,34 +68,35 @@ __global__ void k_imp_stage(const InstDev* __restrict__ inst, int stage,
       const c64 sw = cmulw(d.sigma[e], wj);
       d.g0inv[e] = c64{x0.re + sw.re, x0.im + sw.im};
     } else if (stage == 2) {
-      double s = 0.0;
-      if (j == i - 1) s = 1.0;
-      if (i == 0 && j == n - 1) s = -1.0;
+      double sv = 0.0;
+      if (j == i - 1) sv = 1.0;
+      if (i == 0 && j == n - 1) sv = -1.0;
+      const double dc = (1.0 - d.w1) * d.d1 + d.w1 * d.d0;
       const c64 g = d.g0inv[e];
-      ximp[d.s0 + e] = c64{g.re + d.d0 * s, g.im};
-      ximp[d.s1 + e] = c64{g.re + d.d1 * s, g.im};
-    } else if (stage == 3) {
-      const c64 a = ximp[d.s0 + (size_t)piv[d.i0 + i] * n + rc[d.i0 + j]];
-      const c64 b = ximp[d.s1 + (size_t)piv[d.i1 + i] * n + rc[d.i1 + j]];
-      d.tmp[e] = c64{(1.0 - d.w1) * a.re + d.w1 * b.re, (1.0 - d.w1) * a.im + d.w1 * b.im};
-    } else if (stage == 4) {
-      ximp[d.s0 + e] = d.tmp[e];
+      ximp[d.s0 + e] = c64{g.re + dc * sv, g.im};
     } else {
-      const c64 gi = ximp[d.s0 + (size_t)piv[d.i0 + i] * n + rc[d.i0 + j]];
-      const c64 g = d.g0inv[e];
-      const c64 df{g.re - gi.re, g.im - gi.im};
+      // (S X S)[i][j] = s_i t_j X[i - 1 mod n][j + 1 mod n], X = inv(C) read
+      // through the pivot maps
+      const int k = (i == 0) ? n - 1 : i - 1, l = (j == n - 1) ? 0 : j + 1;
+      const double gam = d.w1 * (1.0 - d.w1) * (d.d0 - d.d1) * (d.d0 - d.d1);
+      const double h = (1.0 - d.w1) * d.d0 + d.w1 * d.d1;
+      const double sg = gam * ((i == 0) ? -1.0 : 1.0) * ((j == n - 1) ? -1.0 : 1.0);
+      const c64 x = ximp[d.s0 + (size_t)piv[d.i0 + k] * n + rc[d.i0 + l]];
+      c64 df{sg * x.re, sg * x.im};
+      if (j == i - 1) df.re -= h;
+      else if (i == 0 && j == n - 1) df.re += h;
       const double den = wj.re * wj.re + wj.im * wj.im;
-      const c64 s{(df.re * wj.re + df.im * wj.im) / den,
-                  (df.im * wj.re - df.re * wj.im) / den};
+      const c64 sn{(df.re * wj.re + df.im * wj.im) / den,
+                   (df.im * wj.re - df.re * wj.im) / den};
       const c64 old = d.sigma[e];
-      const double dr = s.re - old.re, di = s.im - old.im;
+      const double dr = sn.re - old.re, di = sn.im - old.im;
       const double a = sqrt(dr * dr + di * di);
       if (!(a <= 1.79769313486231570815e308)) bad = true;
       else if (a > mx) mx = a;
-      d.sigma[e] = s;
+      d.sigma[e] = sn;
     }
   }
-  if (stage == 5) {
+  if (stage == 3) {
     unsigned long long k = bad ? 0x7ff8000000000000ULL
                                : (unsigned long long)__double_as_longlong(mx);
     for (int off = 32; off >= 1; off >>= 1) {
@@ -150,7 +151,7 @@ struct fk_batch {
   std::vector<int> iters;
   std::vector<double> delta;
   std::vector<Chunk> chunks;
-  fk::Batch<double> impA, impB;   // slot0 of every active instance / both slots
+  fk::Batch<double> impA;   // the impurity slot of every active instance
   // shared storage of the lattice chunks and of the impurity slots
   c64* x = nullptr;
   c64* bbuf = nullptr;
@@ -288,30 +289,25 @@ fk_status build_plan(fk_batch* b) {
       io += n;
     }
   }
-  // impurity slots: slot0 of every active instance, then every slot1
+  // impurity slots: one per active instance
   const int na = (int)b->active.size();
-  std::vector<int> isz(2 * na), isx(2 * na);
+  std::vector<int> isz(na), isx(na);
   size_t xs = 0, bs = 0, is = 0;
-  for (int h = 0; h < 2; ++h)
-    for (int a = 0; a < na; ++a) {
-      const int n = b->inst[b->active[a]]->ci.n_c;
-      isz[h * na + a] = n;
-      isx[h * na + a] = status++;
-      xs += (size_t)n * n;
-      bs += (size_t)kNBO * n;
-      is += n;
-    }
+  for (int a = 0; a < na; ++a) {
+    const int n = b->inst[b->active[a]]->ci.n_c;
+    isz[a] = n;
+    isx[a] = status++;
+    xs += (size_t)n * n;
+    bs += (size_t)kNBO * n;
+    is += n;
+  }
   BCHK(b, grow(&b->xi, &b->xi_cap, xs));
   BCHK(b, grow(&b->bi, &b->bi_cap, bs));
   BCHK(b, grow(&b->pivi, &b->ii_cap, is));
   BCHK(b, grow(&b->rci, &b->ii2_cap, is));
   batch_free(b->impA);
-  batch_free(b->impB);
   borrow(b->impA, b->xi, b->xi_cap, b->bi, b->bi_cap, b->pivi, b->rci, b->ii_cap);
-  borrow(b->impB, b->xi, b->xi_cap, b->bi, b->bi_cap, b->pivi, b->rci, b->ii_cap);
-  BCHK(b, batch_setup_uneven(b->impB, isz, isx));
-  std::vector<int> hsz(isz.begin(), isz.begin() + na), hsx(isx.begin(), isx.begin() + na);
-  BCHK(b, batch_setup_uneven(b->impA, hsz, hsx));
+  BCHK(b, batch_setup_uneven(b->impA, isz, isx));
   b->n_status = status;
   BCHK(b, grow(&b->d_status, &b->status_cap, (size_t)status));
   // instance views
@@ -334,15 +330,12 @@ fk_status build_plan(fk_batch* b) {
     d.sigma = c->d_sigma;
     d.w = c->d_w;
     d.g0inv = c->d_g0inv;
-    d.tmp = c->d_tmp;
     d.n = n;
     d.d0 = c->m.convention == 0 ? 0.5 * c->m.U : 0.0;
     d.d1 = c->m.convention == 0 ? -0.5 * c->m.U : -c->m.U;
     d.w1 = c->m.w1;
     d.s0 = (long long)s0[a];
-    d.s1 = (long long)(so + s0[a]);
     d.i0 = (int)i0[a];
-    d.i1 = (int)(ioff + i0[a]);
     d.key = 2 * b->active[a];
   }
   BCHK(b, grow(&b->d_inst, &b->inst_cap, (size_t)std::max(na, 1)));
@@ -417,15 +410,10 @@ hipError_t record_sweep(fk_batch* b) {
     return e;
   if ((e = launch_imp(b, 1)) != hipSuccess) return e;
   if ((e = launch_imp(b, 2)) != hipSuccess) return e;
-  if ((e = batch_invert<double>(b->impB, 2 * na, b->st, b->aux, nullptr, nullptr,
-                                b->d_status)) != hipSuccess)
-    return e;
-  if ((e = launch_imp(b, 3)) != hipSuccess) return e;
-  if ((e = launch_imp(b, 4)) != hipSuccess) return e;
   if ((e = batch_invert<double>(b->impA, na, b->st, b->aux, nullptr, nullptr,
                                 b->d_status)) != hipSuccess)
     return e;
-  return launch_imp(b, 5);
+  return launch_imp(b, 3);
 }
 
 }  // namespace
@@ -481,7 +469,6 @@ extern "C" fk_status fk_batch_destroy(fk_batch* b) {
   drop_graph(b);
   for (Chunk& c : b->chunks) batch_free(c.b);
   batch_free(b->impA);
-  batch_free(b->impB);
   void* ps[] = {b->x, b->bbuf, b->piv, b->rowcol, b->xi, b->bi, b->pivi, b->rci,
                 b->d_status, b->d_keys, b->d_inst};
   for (void* p : ps)

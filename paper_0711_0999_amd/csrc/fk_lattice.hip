@@ -340,7 +340,8 @@ __global__ void k_add_right_weighted(c64* __restrict__ g0inv,
   }
 }
 
-// slot_m = g0inv + d_m S for m = 0, 1 (S[j][j-1] = 1, S[0][n-1] = -1)
+// slot_m = g0inv + d_m S for m = 0, 1 (S[j][j-1] = 1, S[0][n-1] = -1);
+// x1 may be null (one slot)
 __global__ void k_shifted_pair(const c64* __restrict__ g0inv, double d0,
                                double d1, c64* __restrict__ x0,
                                c64* __restrict__ x1, int ld, int n) {
@@ -355,44 +356,49 @@ __global__ void k_shifted_pair(const c64* __restrict__ g0inv, double d0,
     a.re += d0 * s;
     b.re += d1 * s;
     x0[(size_t)i * ld + j] = a;
-    x1[(size_t)i * ld + j] = b;
+    if (x1) x1[(size_t)i * ld + j] = b;
   }
 }
 
-// sigma_new[i][j] = (g0inv[i][j] - ginv[i][j]) / W_j, and the running max of
-// |sigma_new - sigma_old| via the key of k_maxabs.
-__global__ void k_sigma_new(const c64* __restrict__ g0inv,
-                            const c64* __restrict__ ginv,
-                            const c64* __restrict__ w, c64* __restrict__ sigma,
-                            int n, unsigned long long* __restrict__ key) {
+// Falicov-Kimball self-energy from the one inverse X = C^-1, C = G0^-1 + d_c S:
+// sigma_new W = -h S + gam S X S (the two-inversion form of the paper's
+// G0^-1 - G_imp^-1), sigma_new[i][j] = that / W_j, and the running max of
+// |sigma_new - sigma_old| via the key of k_maxabs.  (S X S)[i][j] =
+// s_i t_j X[i - 1 mod n][j + 1 mod n] with s_0 = t_{n-1} = -1, else 1.
+__global__ void k_sigma_fk(const c64* __restrict__ x, const c64* __restrict__ w,
+                           c64* __restrict__ sigma, int n, double h, double gam,
+                           unsigned long long* __restrict__ key) {
   const size_t total = (size_t)n * n;
   double mx = 0.0;
   bool bad = false;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e - (e / n) * n);
-    c64 d;
-    d.re = g0inv[e].re - ginv[e].re;
-    d.im = g0inv[e].im - ginv[e].im;
+    const int i = (int)(e / n), j = (int)(e - (e / n) * n);
+    const int k = (i == 0) ? n - 1 : i - 1, l = (j == n - 1) ? 0 : j + 1;
+    const double sg = gam * ((i == 0) ? -1.0 : 1.0) * ((j == n - 1) ? -1.0 : 1.0);
+    const c64 v = x[(size_t)k * n + l];
+    c64 d{sg * v.re, sg * v.im};
+    if (j == i - 1) d.re -= h;
+    else if (i == 0 && j == n - 1) d.re += h;
     const c64 wj = w[j];
     const double den = wj.re * wj.re + wj.im * wj.im;
-    c64 s;
-    s.re = (d.re * wj.re + d.im * wj.im) / den;
-    s.im = (d.im * wj.re - d.re * wj.im) / den;
+    c64 sv;
+    sv.re = (d.re * wj.re + d.im * wj.im) / den;
+    sv.im = (d.im * wj.re - d.re * wj.im) / den;
     const c64 old = sigma[e];
-    const double dr = s.re - old.re, di = s.im - old.im;
-    const double v = sqrt(dr * dr + di * di);
-    if (!(v <= 1.79769313486231570815e308)) bad = true;
-    else if (v > mx) mx = v;
-    sigma[e] = s;
+    const double dr = sv.re - old.re, di = sv.im - old.im;
+    const double a = sqrt(dr * dr + di * di);
+    if (!(a <= 1.79769313486231570815e308)) bad = true;
+    else if (a > mx) mx = a;
+    sigma[e] = sv;
   }
-  unsigned long long k = bad ? 0x7ff8000000000000ULL
-                             : (unsigned long long)__double_as_longlong(mx);
+  unsigned long long kk = bad ? 0x7ff8000000000000ULL
+                              : (unsigned long long)__double_as_longlong(mx);
   for (int off = 32; off >= 1; off >>= 1) {
-    const unsigned long long o = __shfl_xor(k, off);
-    k = o > k ? o : k;
+    const unsigned long long o = __shfl_xor(kk, off);
+    kk = o > kk ? o : kk;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(key, k);
+  if ((threadIdx.x & 63) == 0) atomicMax(key, kk);
 }
 
 // ------------------------------------------------------------ launchers ----
@@ -472,12 +478,11 @@ hipError_t launch_shifted_pair(const c64* g0inv, double d0, double d1, c64* x0,
   return hipGetLastError();
 }
 
-hipError_t launch_sigma_new(const c64* g0inv, const c64* ginv, const c64* w,
-                            c64* sigma, int n, unsigned long long* key,
-                            hipStream_t st) {
+hipError_t launch_sigma_fk(const c64* x, const c64* w, c64* sigma, int n, double h,
+                           double gam, unsigned long long* key, hipStream_t st) {
   const int g = grid_for((size_t)n * n, 256);
-  hipLaunchKernelGGL(k_sigma_new, dim3(g > 2048 ? 2048 : g), dim3(256), 0, st,
-                     g0inv, ginv, w, sigma, n, key);
+  hipLaunchKernelGGL(k_sigma_fk, dim3(g > 2048 ? 2048 : g), dim3(256), 0, st, x, w,
+                     sigma, n, h, gam, key);
   return hipGetLastError();
 }
 

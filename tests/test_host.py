@@ -149,3 +149,34 @@ def test_spectral_entry_points_reject_null_arguments(lib):
     assert L.fk_wigner_dos(None, 1, ti, 1, om, out) == lib.FK_EINVAL
     assert L.fk_equal_time_moments(None, 1, ti, out) == lib.FK_EINVAL
     assert L.fk_get_zeroth_moment(None, out) == lib.FK_EINVAL
+
+
+@pytest.mark.parametrize("convention,w1", [("symmetric", 0.5), ("paper", 0.5),
+                                            ("symmetric", 0.3)])
+def test_impurity_update_two_inversion_identity(convention, w1):
+    """The library's impurity update needs two inversions instead of four:
+    with A_m = G0^-1 + d_m S (the point-split shifts, S[j][j-1] = 1,
+    S[0][n-1] = -1) and C = (1 - w1) A_1 + w1 A_0 = G0^-1 + d_c S, one has
+    [(1 - w1) A_0^-1 + w1 A_1^-1]^-1 = A_1 C^-1 A_0, hence
+    Sigma_new W = -h S + w1 (1 - w1) (d0 - d1)^2 S C^-1 S with
+    h = (1 - w1) d0 + w1 d1.  Checked against the oracle's update (the
+    paper's sequence of inversions) on a random contour matrix."""
+    from oracle import contour as oc, impurity
+    rng = np.random.default_rng(17)
+    z, w = oc.points(-1.0, 1.0, 0.2, 0.2, 1.0)
+    n = len(w)
+    gloc = 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) \
+        + 0.5j * np.eye(n)
+    sigma = 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    u, mu = 1.3, (0.0 if convention == "symmetric" else 0.65)
+    ref = impurity.update(gloc, sigma, w, mu, u, w1, convention)
+    d0, d1 = impurity.shifts(u, convention)
+    s = np.zeros((n, n))
+    s[np.arange(1, n), np.arange(0, n - 1)] = 1.0
+    s[0, n - 1] = -1.0
+    g0inv = np.linalg.inv(gloc * w[None, :]) + sigma * w[None, :]
+    dc = (1 - w1) * d1 + w1 * d0
+    h = (1 - w1) * d0 + w1 * d1
+    cinv = np.linalg.inv(g0inv + dc * s)
+    new_r = -h * s + w1 * (1 - w1) * (d0 - d1) ** 2 * (s @ cinv @ s)
+    np.testing.assert_allclose(new_r / w[None, :], ref, rtol=1e-10, atol=1e-10)
