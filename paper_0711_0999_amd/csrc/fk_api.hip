@@ -398,18 +398,13 @@ fk_status impurity(fk_ctx* c, double* dsig) {
   int launches = 0;
   fk_status s;
   HIPCHK(c, hipEventRecord(c->ev[4], c->st));
-  // g0inv = (G_loc W)^-1 + Sigma W
-  HIPCHK(c, launch_right_weight(c->d_gloc, c->d_w, b.x, b.ld, n, c->st));
-  HIPCHK(c, batch_invert<double>(b, 1, c->st, c->aux, &launches));
-  if ((s = check_status(c, b.status, 1, 0, "inverse of G_loc W")) != FK_OK) return s;
-  HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
-                                  c->d_coef, 1, n, c->d_g0inv, 0, c->st));
-  HIPCHK(c, launch_add_right_weighted(c->d_g0inv, c->d_sigma, c->d_w, n, c->st));
-  // G_imp = (1 - w1) A0^-1 + w1 A1^-1 with A_m = g0inv + d_m S has the inverse
-  // A1 C^-1 A0, C = (1 - w1) A1 + w1 A0 = g0inv + d_c S, so that
-  //   Sigma_new W = g0inv - G_imp^-1 = -h S + w1 (1 - w1) (d0 - d1)^2 S C^-1 S,
-  // h = (1 - w1) d0 + w1 d1: one inversion instead of the pair and the
-  // inverse of their combination.
+  // G0^-1 = (G_loc W)^-1 + Sigma W.  G_imp = (1 - w1) A0^-1 + w1 A1^-1 with
+  // A_m = G0^-1 + d_m S has the inverse A1 C^-1 A0, C = (1 - w1) A1 + w1 A0 =
+  // G0^-1 + d_c S, so that
+  //   Sigma_new W = G0^-1 - G_imp^-1 = -h S + w1 (1 - w1) (d0 - d1)^2 S C^-1 S,
+  // h = (1 - w1) d0 + w1 d1; and with X = G_loc W, Y = Sigma W + d_c S,
+  //   C^-1 = (X^-1 + Y)^-1 = X (I + Y X)^-1:
+  // one inversion and two products instead of the paper's four inversions.
   double d0, d1;
   if (c->m.convention == 0) {
     d0 = 0.5 * c->m.U;
@@ -421,14 +416,20 @@ fk_status impurity(fk_ctx* c, double* dsig) {
   const double w1 = c->m.w1;
   const double dc = (1.0 - w1) * d1 + w1 * d0, h = (1.0 - w1) * d0 + w1 * d1;
   const double gam = w1 * (1.0 - w1) * (d0 - d1) * (d0 - d1);
-  HIPCHK(c, launch_shifted_pair(c->d_g0inv, dc, dc, b.x, nullptr, b.ld, n, c->st));
+  c64* X = c->d_g0inv;   // impurity scratch
+  HIPCHK(c, launch_right_weight(c->d_gloc, c->d_w, X, n, n, c->st));
+  HIPCHK(c, launch_right_weight(c->d_sigma, c->d_w, c->d_tmp, n, n, c->st));
+  HIPCHK(c, launch_bgemm(b.x, nullptr, 0.0, c->d_tmp, 0, X, n, 1, c->st));
+  HIPCHK(c, launch_add_identity_shift(b.x, b.ld, X, dc, n, c->st));
   HIPCHK(c, batch_invert<double>(b, 1, c->st, c->aux, &launches));
-  if ((s = check_status(c, b.status, 1, 0, "inverse of the combined resolvent")) != FK_OK)
+  if ((s = check_status(c, b.status, 1, 0, "inverse of I + (Sigma W + d S) G_loc W")) !=
+      FK_OK)
     return s;
   HIPCHK(c, launch_reduce<double>(b.x, b.stride, b.ld, b.piv, b.rowcol, n,
                                   c->d_coef, 1, n, c->d_tmp, 0, c->st));
+  HIPCHK(c, launch_bgemm(b.x, nullptr, 0.0, X, 0, c->d_tmp, n, 1, c->st));
   HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
-  HIPCHK(c, launch_sigma_fk(c->d_tmp, c->d_w, c->d_sigma, n, h, gam, c->d_key, c->st));
+  HIPCHK(c, launch_sigma_fk(b.x, c->d_w, c->d_sigma, n, h, gam, c->d_key, c->st));
   HIPCHK(c, hipEventRecord(c->ev[5], c->st));
   double mx = read_key(c, &s);
   if (s != FK_OK) return s;

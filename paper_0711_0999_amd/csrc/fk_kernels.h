@@ -58,6 +58,9 @@ hipError_t launch_add_right_weighted(c64* g0inv, const c64* sigma, const c64* w,
                                      int n, hipStream_t st);
 hipError_t launch_shifted_pair(const c64* g0inv, double d0, double d1, c64* x0,
                                c64* x1, int ld, int n, hipStream_t st);
+// slot += I + d S X (X natural, n x n; slot with leading dimension ld)
+hipError_t launch_add_identity_shift(c64* slot, int ld, const c64* x, double d, int n,
+                                     hipStream_t st);
 // sigma_new = (-h S + gam S X S) W^-1 from X = (G0^-1 + d_c S)^-1 (natural layout)
 hipError_t launch_sigma_fk(const c64* x, const c64* w, c64* sigma, int n, double h,
                            double gam, unsigned long long* key, hipStream_t st);

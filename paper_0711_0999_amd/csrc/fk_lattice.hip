@@ -360,6 +360,29 @@ __global__ void k_shifted_pair(const c64* __restrict__ g0inv, double d0,
   }
 }
 
+// slot[i][j] += delta_ij + d (S X)[i][j], (S X)[i][j] = s_i X[i - 1 mod n][j]
+// (s_0 = -1, else 1): the sparse part of I + (Sigma W + d S) X, X natural.
+__global__ void k_add_identity_shift(c64* __restrict__ slot, int ld,
+                                     const c64* __restrict__ x, double d, int n) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int k = (i == 0) ? n - 1 : i - 1;
+  const double sg = (i == 0) ? -d : d;
+  const c64 v = x[(size_t)k * n + j];
+  c64 a = slot[(size_t)i * ld + j];
+  a.re += sg * v.re + (j == i ? 1.0 : 0.0);
+  a.im += sg * v.im;
+  slot[(size_t)i * ld + j] = a;
+}
+
+hipError_t launch_add_identity_shift(c64* slot, int ld, const c64* x, double d, int n,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(k_add_identity_shift, dim3((n + 255) / 256, n), dim3(256), 0, st,
+                     slot, ld, x, d, n);
+  return hipGetLastError();
+}
+
 // Falicov-Kimball self-energy from the one inverse X = C^-1, C = G0^-1 + d_c S:
 // sigma_new W = -h S + gam S X S (the two-inversion form of the paper's
 // G0^-1 - G_imp^-1), sigma_new[i][j] = that / W_j, and the running max of

@@ -153,14 +153,15 @@ def test_spectral_entry_points_reject_null_arguments(lib):
 
 @pytest.mark.parametrize("convention,w1", [("symmetric", 0.5), ("paper", 0.5),
                                             ("symmetric", 0.3)])
-def test_impurity_update_two_inversion_identity(convention, w1):
-    """The library's impurity update needs two inversions instead of four:
+def test_impurity_update_single_inversion_identity(convention, w1):
+    """The library's impurity update needs one inversion instead of four:
     with A_m = G0^-1 + d_m S (the point-split shifts, S[j][j-1] = 1,
     S[0][n-1] = -1) and C = (1 - w1) A_1 + w1 A_0 = G0^-1 + d_c S, one has
     [(1 - w1) A_0^-1 + w1 A_1^-1]^-1 = A_1 C^-1 A_0, hence
     Sigma_new W = -h S + w1 (1 - w1) (d0 - d1)^2 S C^-1 S with
-    h = (1 - w1) d0 + w1 d1.  Checked against the oracle's update (the
-    paper's sequence of inversions) on a random contour matrix."""
+    h = (1 - w1) d0 + w1 d1, and C^-1 = X (I + Y X)^-1 with X = G_loc W,
+    Y = Sigma W + d_c S.  Checked against the oracle's update (the paper's
+    sequence of inversions) on a random contour matrix."""
     from oracle import contour as oc, impurity
     rng = np.random.default_rng(17)
     z, w = oc.points(-1.0, 1.0, 0.2, 0.2, 1.0)
@@ -180,3 +181,10 @@ def test_impurity_update_two_inversion_identity(convention, w1):
     cinv = np.linalg.inv(g0inv + dc * s)
     new_r = -h * s + w1 * (1 - w1) * (d0 - d1) ** 2 * (s @ cinv @ s)
     np.testing.assert_allclose(new_r / w[None, :], ref, rtol=1e-10, atol=1e-10)
+    # and the single-inversion form the library takes:
+    # C^-1 = (X^-1 + Y)^-1 = X (I + Y X)^-1, X = G_loc W, Y = Sigma W + d_c S
+    x = gloc * w[None, :]
+    y = sigma * w[None, :] + dc * s
+    cinv1 = x @ np.linalg.inv(np.eye(n) + y @ x)
+    new_r1 = -h * s + w1 * (1 - w1) * (d0 - d1) ** 2 * (s @ cinv1 @ s)
+    np.testing.assert_allclose(new_r1 / w[None, :], ref, rtol=1e-10, atol=1e-10)
