@@ -180,8 +180,11 @@ fk_status fk_equal_time_moments(const fk_ctx* ctx, int n_T, const int* t_index,
  *   G_imp = (1-w1) (g0inv + d0 S)^-1 + w1 (g0inv + d1 S)^-1
  *   Sigma <- (g0inv - G_imp^-1) W^-1
  * with S the point-split delta (S[j,j-1] = 1, S[0,N_c-1] = -1) and (d0, d1)
- * from the model's convention.  Complex128 Gauss-Jordan inversions on the
- * device.  max_dsigma_out (nullable) = max |Sigma_new - Sigma_old|.
+ * from the model's convention.  The same value is reached with one complex128
+ * Gauss-Jordan inversion on the device: with X = G_loc W, Y = Sigma W + d_c S,
+ * d_c = (1-w1) d1 + w1 d0 and h = (1-w1) d0 + w1 d1,
+ *   Sigma W <- -h S + w1 (1-w1) (d0-d1)^2 S X (I + Y X)^-1 S.
+ * max_dsigma_out (nullable) = max |Sigma_new - Sigma_old|.
  * FK_ESTATE before any lattice step. */
 fk_status fk_impurity_update(fk_ctx* ctx, double* max_dsigma_out);
 
