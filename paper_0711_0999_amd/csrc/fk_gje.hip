@@ -201,14 +201,8 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
   }
 }
 
-// Column groups of 8 columns updated per batch of loads in the panel's rank-IB
-// updates (bounded by registers: IB complex values per group; twice the
-// groups for IB = 4).
-template <typename T> struct GroupBatch { static constexpr int value = 4; };
-template <> struct GroupBatch<float> { static constexpr int value = 7; };
-
 // ---------------------------------------------------- panel: factorization
-// Eliminate the PW (32 or 64) columns starting at c0 on the listed rows
+// Eliminate the PW (32) columns starting at c0 on the listed rows
 // rows[0, m) (the rows not pivoted before this outer block) with partial
 // pivoting, IB columns at a time in registers.  Thread tid owns list entries
 // tid + i * kPanelThreads, i < RPT; the list is in ascending row order, so a
@@ -230,8 +224,6 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cw = min(PW, n - c0);
   const T inf_key = big_value<T>();
-  constexpr int kGBr = GroupBatch<T>::value * 8 / IB, kGBo = PW / IB - 1;
-  constexpr int kGB = (kGBr < kGBo ? kGBr : kGBo) > 0 ? (kGBr < kGBo ? kGBr : kGBo) : 1;
 
   // bit i: list entry tid + i kPanelThreads is pivoted (or absent); row ids
   // are re-read from the LDS list where needed (registers go to v)
@@ -384,56 +376,52 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       Bo[e] = t;
     }
     __syncthreads();
-    // ---- rank-iw update of the other column groups of the panel on the rows
-    // this thread owns and has just written: each row's eliminated values are
-    // read back once (same thread, program order) and applied to every other
-    // group of the row.
-    const int cur = b0 / IB;
-    int pv0[IB];
+    // ---- rank-iw update of the other column groups of the panel: 16 lanes
+    // per row (lane k holds columns k and k + 16 of the panel), four rows per
+    // wave at a time, so each load and store of a wave covers four rows'
+    // contiguous segments instead of one cache line per lane; a row's
+    // eliminated values come from the lanes holding them (16-wide shuffles).
+    if (ngroups > 1) {
+      static_assert(PW == 32 && 16 % IB == 0, "panel lane map");
+      const int k16 = lane & 15, rr = lane >> 4;
+      const int ca = k16, cb = k16 + 16;
+      const bool sta = ca < cw && !(ca >= b0 && ca < b0 + IB);
+      const bool stb = cb < cw && !(cb >= b0 && cb < b0 + IB);
+      cplx<T> boa[IB], bob[IB];
+      int pv0[IB];
 #pragma unroll
-    for (int l = 0; l < IB; ++l) pv0[l] = (l < iw) ? pvt[l] : -1;
+      for (int l = 0; l < IB; ++l) {
+        boa[l] = Bo[l * PW + ca];
+        bob[l] = Bo[l * PW + cb];
+        pv0[l] = (l < iw) ? pvt[l] : -1;
+      }
+      const int src0 = b0 & 15;          // lane holding column b0 of the row
+      const bool hi = b0 >= 16;          // ... in its second value
 #pragma unroll 1
-    for (int i = 0; i < RPT; ++i) {
-      const int e = tid + i * kPanelThreads;
-      if (e >= m) break;
-      const int r = rows[e];
-      bool isp = false;
+      for (int e0 = 4 * wave; e0 < m; e0 += 4 * kPW) {
+        const int e = e0 + rr;
+        const int r = rows[min(e, m - 1)];
+        const cplx<T> va = x[(size_t)r * ld + c0 + min(ca, cw - 1)];
+        const cplx<T> vb = x[(size_t)r * ld + c0 + min(cb, cw - 1)];
+        bool isp = false;
 #pragma unroll
-      for (int l = 0; l < IB; ++l) isp |= (pv0[l] == r);
-      cplx<T> mm[IB];
+        for (int l = 0; l < IB; ++l) isp |= (pv0[l] == r);
+        cplx<T> acca = va, accb = vb;
+        if (isp) acca.re = acca.im = accb.re = accb.im = T(0);
+        const cplx<T> src = hi ? vb : va;
 #pragma unroll
-      for (int l = 0; l < IB; ++l) mm[l] = x[(size_t)r * ld + c0 + b0 + min(l, iw - 1)];
-      // the other groups in batches of kGB whose loads are all in flight
-      // together (a group index past the panel reads the current group and
-      // stores nothing)
-#pragma unroll 1
-      for (int q0 = 0; q0 < PW / IB - 1; q0 += kGB) {
-        cplx<T> od[kGB][IB];
-        int cgs[kGB], gws[kGB];
-        bool ok[kGB];
-#pragma unroll
-        for (int q = 0; q < kGB; ++q) {
-          int g = q0 + q;
-          g += (g >= cur) ? 1 : 0;
-          ok[q] = (q0 + q < PW / IB - 1) && g < ngroups;
-          cgs[q] = (ok[q] ? g : cur) * IB;
-          gws[q] = min(IB, cw - cgs[q]);
-#pragma unroll
-          for (int cc = 0; cc < IB; ++cc)
-            od[q][cc] = x[(size_t)r * ld + c0 + cgs[q] + min(cc, gws[q] - 1)];
-        }
-#pragma unroll
-        for (int q = 0; q < kGB; ++q) {
-          if (!ok[q]) continue;
-#pragma unroll
-          for (int cc = 0; cc < IB; ++cc) {
-            cplx<T> acc = od[q][cc];
-            if (isp) acc.re = acc.im = T(0);
-#pragma unroll
-            for (int l = 0; l < IB; ++l)
-              if (l < iw) cfma(acc, mm[l], Bo[l * PW + cgs[q] + cc]);
-            if (cc < gws[q]) x[(size_t)r * ld + c0 + cgs[q] + cc] = acc;
+        for (int l = 0; l < IB; ++l) {
+          if (l < iw) {
+            cplx<T> mm;
+            mm.re = __shfl(src.re, src0 + l, 16);
+            mm.im = __shfl(src.im, src0 + l, 16);
+            cfma(acca, mm, boa[l]);
+            cfma(accb, mm, bob[l]);
           }
+        }
+        if (e < m) {
+          if (sta) x[(size_t)r * ld + c0 + ca] = acca;
+          if (stb) x[(size_t)r * ld + c0 + cb] = accb;
         }
       }
     }
