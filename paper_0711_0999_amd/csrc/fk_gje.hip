@@ -162,7 +162,10 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
       if (!(r0 + i < m && l < w)) v.re = v.im = T(0);
       Ms[i * KP + l] = v;
     }
-    v4 cr[RB], ci[RB];
+    // masked C (pivot rows of the block start from zero); the product is
+    // formed from three real ones (Gauss) as in the trailing update:
+    // P1 = Re a Re b, P2 = Im a Im b, P3 = (Re a + Im a)(Re b + Im b),
+    // Re = P1 - P2, Im = P3 - P1 - P2, and C added afterwards
 #pragma unroll
     for (int ii = 0; ii < RB; ++ii)
 #pragma unroll
@@ -170,20 +173,24 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
         const int e = r0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
         const bool keep = e < m && col < cw &&
                           !(rcv[ii][v] >= j0 && rcv[ii][v] < j0 + w);
-        cr[ii][v] = keep ? cv[ii][v].re : T(0);
-        ci[ii][v] = keep ? cv[ii][v].im : T(0);
+        if (!keep) cv[ii][v].re = cv[ii][v].im = T(0);
       }
+    v4 p1[RB], p2[RB], p3[RB];
+#pragma unroll
+    for (int ii = 0; ii < RB; ++ii)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) p1[ii][v] = p2[ii][v] = p3[ii][v] = T(0);
     __syncthreads();
 #pragma unroll 4
     for (int k = 0; k < KW; k += 4) {
       const cplx<T> b = Bs[(k + lk) * CP + col];
+      const T bs = b.re + b.im;
 #pragma unroll
       for (int ii = 0; ii < RB; ++ii) {
         const cplx<T> a = Ms[(16 * (RB * wr + ii) + li) * KP + k + lk];
-        cr[ii] = Mfma<T>::run(a.re, b.re, cr[ii]);
-        ci[ii] = Mfma<T>::run(a.re, b.im, ci[ii]);
-        cr[ii] = Mfma<T>::run(-a.im, b.im, cr[ii]);
-        ci[ii] = Mfma<T>::run(a.im, b.re, ci[ii]);
+        p1[ii] = Mfma<T>::run(a.re, b.re, p1[ii]);
+        p2[ii] = Mfma<T>::run(a.im, b.im, p2[ii]);
+        p3[ii] = Mfma<T>::run(a.re + a.im, bs, p3[ii]);
       }
     }
 #pragma unroll
@@ -192,9 +199,10 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
       for (int v = 0; v < 4; ++v) {
         const int e = r0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
         if (e < m && col < cw) {
+          const T q1 = p1[ii][v], q2 = p2[ii][v];
           cplx<T> c;
-          c.re = cr[ii][v];
-          c.im = ci[ii][v];
+          c.re = (q1 - q2) + cv[ii][v].re;
+          c.im = ((p3[ii][v] - q1) - q2) + cv[ii][v].im;
           x[(size_t)rid[ii][v] * ld + c0 + col] = c;
         }
       }
