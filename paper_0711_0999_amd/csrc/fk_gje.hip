@@ -4,13 +4,14 @@
 // "matrix inversion" of the integrand of eq. g_loc, Sec. II).
 //
 // Outer step S handles the block of kNBO = 128 columns starting at J0 = S*kNBO:
-//   panel   (one 512-thread workgroup per matrix) eliminates the block's two
-//           64-column inner panels in turn on the n - J0 rows not pivoted in
+//   panel   (one 512-thread workgroup per matrix) eliminates the block's
+//           four 32-column quarters in turn on the n - J0 rows not pivoted in
 //           earlier blocks.  For each column the pivot is the largest
 //           |re|+|im| among the rows not yet pivoted; kIB columns are
-//           eliminated in registers at a time, the rest of the inner panel
-//           receives rank-kIB updates row by row, and the other inner panel
-//           the rank-64 transform on the matrix cores.
+//           eliminated in registers at a time (one row per thread), the rest
+//           of the quarter receives rank-kIB updates (16 lanes per row), and
+//           the other quarter of the half and then the other half receive
+//           the quarter's (half's) transform on the matrix cores.
 //   gather  copies the pivot rows of the step into a side buffer B (their
 //           values before the step outside the block, the block's inverse
 //           pivot submatrix inside it).
@@ -21,8 +22,9 @@
 //   update  every other column tile: C <- mask_P(C) + M B (K = 128), a batched
 //           complex GEMM on the matrix cores (three real products per complex
 //           one), double-buffered K chunks in LDS, two workgroups per CU.
-// The host runs the update of the next block's columns first and factors that
-// block on a second stream while the big update of the current step runs.
+// The host runs the update of the next block's columns first; with the
+// look-ahead schedule it factors that block on a second stream while the big
+// update of the current step runs.
 // Rows are never swapped: with r = piv and rinv = rowcol the inverse is
 // inv(A)[a][b] = X[r[a]][rinv[b]], which the reduction kernels read directly.
 #include "fk_internal.h"
