@@ -131,9 +131,9 @@ def main():
                     help="autotuner byte budget (default 48 GiB, 96 GiB for the long contour)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not "
-              "supported (the k-point sharding across GPUs is described in the "
-              "design notes, not implemented).", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not "
+              "supported (sharding the k-points across GPUs is not implemented).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -24,8 +24,7 @@ Modules (each function cites the passage it follows):
   sketch      randomized range finder / SVD used for the Sigma sketch
 
 Readings of the paper (where it is silent, garbled or ambiguous) are stated in
-the docstrings of the functions that take them; the list is repeated in the
-repository's design notes.
+the docstrings of the functions that take them.
 
 Parity status: every function here is pinned by a test in tests/test_oracle_*.py
 against closed forms, special cases, library routines or brute force, except
