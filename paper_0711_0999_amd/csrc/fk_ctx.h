@@ -50,7 +50,7 @@ struct fk_ctx {
 
   fk::Batch<double> b64;           // lattice batch (complex128)
   fk::Batch<float> b32;            // lattice batch (complex64), lazily
-  fk::Batch<double> imp;           // impurity inversions (2 slots)
+  fk::Batch<double> imp;           // the impurity update's inversion (1 slot)
   fk::Aux aux;                     // look-ahead stream and events
   fk::KernelClock clk;             // optional timing of the trailing update
   // FP64 refinement buffers of the mixed path (ir_cap matrices)
