@@ -205,12 +205,19 @@ def _lattice_gloc(u=1.0, efield=1.0):
     return gl, sig, w
 
 
-def test_impurity_empty_and_full_f_site():
+IMPURITY_FORMS = [pytest.param("update", id="complex128"),
+                  pytest.param("update_extended", id="long-double")]
+
+
+@pytest.mark.parametrize("form", IMPURITY_FORMS)
+def test_impurity_empty_and_full_f_site(form):
     """eq. (g_imp_solve) with <w1> = 0 or 1 is a single level in a static
     potential, so Sigma is that potential whatever G_loc and Sigma were:
     Sigma W = -(mu0 - mu) S for w1 = 0 and -(mu1 - mu) S for w1 = 1 (S the
     point-split delta).  Symmetric convention: -U/2 and +U/2; the paper's
-    literal convention: 0 and +U."""
+    literal convention: 0 and +U.  Both evaluations of the update: complex128
+    and long double."""
+    update = getattr(impurity, form)
     gl, sig, w = _lattice_gloc()
     n = len(w)
     s = np.zeros((n, n), dtype=np.complex128)
@@ -219,14 +226,51 @@ def test_impurity_empty_and_full_f_site():
     u = 1.3
     for w1, conv, expect in [(0.0, "symmetric", -0.5 * u), (1.0, "symmetric", 0.5 * u),
                              (0.0, "paper", 0.0), (1.0, "paper", u)]:
-        got = impurity.update(gl, sig, w, 0.0, u, w1, conv) * w[None, :]
+        got = update(gl, sig, w, 0.0, u, w1, conv) * w[None, :]
         assert np.max(np.abs(got - expect * s)) < 1e-9, (w1, conv)
 
 
-def test_impurity_u0_returns_zero():
+@pytest.mark.parametrize("form", IMPURITY_FORMS)
+def test_impurity_u0_returns_zero(form):
     gl, sig, w = _lattice_gloc()
-    got = impurity.update(gl, sig, w, 0.0, 0.0, 0.5)
+    got = getattr(impurity, form)(gl, sig, w, 0.0, 0.0, 0.5)
     assert np.max(np.abs(got)) < 1e-8
+
+
+def test_extended_inverse_of_the_sparse_propagator_inverse():
+    """The long-double Gauss-Jordan inverse (impurity_ext.c) returns the
+    sampled noninteracting G0 from its exact bidiagonal-plus-corner inverse
+    i D (I - P + e^{-beta(eps - mu)} e_0 e_{N-1}^T) D^-1 (Sherman-Morrison on
+    eq. g_contour_non_final2), and A X = I for a random matrix (to the rounding
+    of the complex128 result)."""
+    z, w = contour.points(-1.0, 1.5, 0.1, 0.25, 2.0)
+    n_t = contour.sizes(-1.0, 1.5, 0.1, 0.25, 2.0)[0]
+    eps, ebar, mu, beta = 0.4, -0.7, 0.1, 2.0
+    g0 = green.g0_matrix(z, n_t, 1.3, mu, beta, eps, ebar)
+    alpha, gamma = green.phase_tables(z, n_t, 1.3)
+    d = np.exp(-1j * (eps * alpha + ebar * gamma) + 1j * mu * z)
+    n = len(z)
+    core = np.eye(n, dtype=np.complex128)
+    core[np.arange(1, n), np.arange(n - 1)] = -1.0
+    core[0, n - 1] = np.exp(-beta * (eps - mu))
+    g0inv = 1j * d[:, None] * core / d[None, :]
+    got = impurity.inverse_extended(g0inv)
+    assert np.max(np.abs(got - g0)) < 1e-14
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal((40, 40)) + 1j * rng.standard_normal((40, 40))
+    x = impurity.inverse_extended(a)
+    assert np.max(np.abs(x @ a - np.eye(40))) < 1e-13
+
+
+def test_extended_update_agrees_with_complex128_on_a_small_contour():
+    """On a small contour the complex128 update loses little to the Dyson
+    subtraction, so the long-double evaluation of the same sequence agrees
+    with it to the complex128 rounding; both conventions and w1 != 1/2."""
+    gl, sig, w = _lattice_gloc()
+    for conv, w1 in (("symmetric", 0.5), ("paper", 0.3)):
+        a = impurity.update(gl, sig, w, 0.0, 1.1, w1, conv)
+        b = impurity.update_extended(gl, sig, w, 0.0, 1.1, w1, conv)
+        assert np.max(np.abs(a - b)) / np.max(np.abs(b)) < 1e-12
 
 
 # ------------------------------------------------------------------- lattice
@@ -417,7 +461,8 @@ def test_c1_reference_delta_history():
     assert 1e-8 < d[-1] < 1e-7
 
 
-def test_impurity_second_order_perturbation():
+@pytest.mark.parametrize("form", IMPURITY_FORMS)
+def test_impurity_second_order_perturbation(form):
     """Weak coupling of eq. (g_imp_solve): expanding both resolvents in the
     shifts +-U/2 gives the textbook Falicov-Kimball result
         Sigma = U (w1 - 1/2) delta + U^2 w1 (1 - w1) G0_eff + O(U^3),
@@ -434,7 +479,7 @@ def test_impurity_second_order_perturbation():
     w1 = 0.3
     rem = []
     for u in (0.02, 0.01):
-        got = impurity.update(gl, sig, w, 0.0, u, w1) * w[None, :]
+        got = getattr(impurity, form)(gl, sig, w, 0.0, u, w1) * w[None, :]
         pred = u * (w1 - 0.5) * s + u * u * w1 * (1 - w1) * (s @ g0eff_r @ s)
         rem.append(np.max(np.abs(got - pred)))
     assert rem[0] / rem[1] > 6.0, rem
@@ -576,6 +621,54 @@ def test_warm_start_feature_rows_by_hand():
     want[2, :61] = ([0.7, 1, 0, 0, 1, 0, 0, -0.25, 0, 0.25, 0, 0, 0, -0.5, 0.25,
                      0, 1, s1, c1, 0, -0.5] + f_minus + f_quarter + f_zero2 + f_zero2)
     assert np.max(np.abs(rows - want)) < 1e-15
+
+
+def test_warm_start_targets_by_hand():
+    """Training targets t = scale (Sigma_new - Sigma_prev) at pair p = i N_c + j
+    (row-major: pair 1 is (0, 1), pair 2 is (1, 0)), worked by hand on a
+    non-symmetric 2 x 2 example, so a transposed pair index, a sign or a
+    missing scale fails."""
+    from oracle import warmstart
+    prev = np.array([[1 + 2j, 0], [3j, -1]])
+    new = np.array([[2 + 2j, 1j], [0, -1]])
+    t = warmstart.targets(prev, new, None, 2.0)
+    want = np.array([[2.0, 0.0], [0.0, 2.0], [0.0, -6.0], [0.0, 0.0]])
+    assert np.array_equal(t, want)
+    t2 = warmstart.targets(prev, new, [2, 1], 0.5)
+    assert np.array_equal(t2, np.array([[0.0, -1.5], [0.0, 0.5]]))
+
+
+def test_warm_start_apply_by_hand_and_inverts_targets():
+    """The update Sigma_prev + y / scale with y the (Re, Im) rows of all pairs
+    in row-major order, worked by hand; and applying the targets of a pair of
+    matrices to the first reproduces the second (the two are inverse maps)."""
+    from oracle import warmstart
+    prev = np.array([[1 + 2j, 0], [3j, -1]])
+    y = np.array([[2.0, 0.0], [0.0, 2.0], [0.0, -6.0], [4.0, 0.0]])
+    got = warmstart.apply(prev, y, 2.0)
+    want = np.array([[2 + 2j, 1j], [0, 1]])
+    assert np.array_equal(got, want)
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5))
+    b = rng.standard_normal((5, 5)) + 1j * rng.standard_normal((5, 5))
+    back = warmstart.apply(a, warmstart.targets(a, b, None, 8.0), 8.0)
+    assert np.max(np.abs(back - b)) < 1e-14
+
+
+def test_coarse_grid_sampling_hits_the_coarse_times():
+    """Samples on the coarse grid t_min + i dt_c of a quantity tabulated at
+    t_min + i dt (dt_c = s dt): taking the fine times themselves as the values,
+    the samples are exactly the coarse times, so an off-by-one in the stride
+    or the start fails; the length is the coarse point count."""
+    from oracle import extrapolate
+    t_min, dt, n_fine = -2.0, 0.05, 80
+    t_fine = t_min + dt * np.arange(n_fine)
+    for dt_c, n_c in ((0.2, 20), (0.1, 40), (0.05, 80)):
+        got = extrapolate.on_coarse_grid(t_fine, dt, dt_c, n_c)
+        assert len(got) == n_c
+        assert np.max(np.abs(got - (t_min + dt_c * np.arange(n_c)))) < 1e-12
+    # fewer coarse points than the fine array holds: truncated at n_coarse
+    assert len(extrapolate.on_coarse_grid(t_fine, dt, 0.2, 7)) == 7
 
 
 def test_splitmix64_published_sequence():
