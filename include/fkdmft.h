@@ -79,7 +79,7 @@ typedef struct {
 /* Gauss-Hermite rule for the normalized Gaussian weight exp(-x^2)/sqrt(pi)
  * (eq. joint_dos, Sec. II quadrature paragraph): n nodes x[n] (ascending) and
  * weights w[n] summing to 1.  Nodes by Sturm-sequence bisection on the Jacobi
- * matrix, weights by the Christoffel formula.  1 <= n <= 400. */
+ * matrix, weights by the Christoffel formula.  1 <= n <= 150, else FK_EINVAL. */
 fk_status fk_gauss_hermite(int n, double* x, double* w);
 
 /* Contour sizes and points without a context: dims[3] = {N_t, N_tau, N_c};
@@ -134,9 +134,13 @@ fk_status fk_get_gloc(const fk_ctx* ctx, double* gloc, int on_device);
  * FK_FP64: complex128 throughout.  FK_MIXED: complex64 inversion, then
  * ir_steps (fk_set_refinement, default 1) FP64 refinement steps
  * X <- X + X (I - A X) with the residual I - A X in FP64; the rho-weighted sum
- * is FP64.  ir_resid_out (nullable) receives max_k max|I - A_k X_k| of the last
- * refinement (FK_FP64: 0).  Errors: FK_ESINGULAR (point index in detail),
- * FK_ENONFINITE. */
+ * is FP64.  ir_resid_out (nullable) receives a bound on max_k max|I - A_k X_k|
+ * of the returned inverses: with r the largest residual entry entering the last
+ * refinement step, the returned X has the residual R^2 (Newton's step), whose
+ * entries are at most N_c r^2 (FK_FP64: 0).  A failed step leaves no G_loc
+ * (fk_get_gloc, fk_get_current and fk_impurity_update return FK_ESTATE until a
+ * step succeeds).  Errors: FK_ESINGULAR ("zero pivot at column c of matrix k",
+ * k the point index), FK_ENONFINITE. */
 fk_status fk_compute_gloc(fk_ctx* ctx, fk_precision prec, double* ir_resid_out);
 
 /* Refinement steps used by FK_MIXED (0..4). */
@@ -203,8 +207,9 @@ fk_status fk_set_switch(fk_ctx* ctx, double switch_tol);
 /* G_k of one quadrature point k (N_c x N_c complex128 values, row-major) as the
  * last FP64 fk_compute_gloc computed it: available for the points of the last
  * batch of that step, which stay in the batch buffers (fk_points gives their
- * (eps, ebar, rho)); otherwise, or after a mixed step, FK_ESTATE.  For parity
- * checks of single points at full size. */
+ * (eps, ebar, rho)); otherwise FK_ESTATE: after a mixed step, a failed step,
+ * fk_set_batch, fk_set_tuning or fk_autotune (each may free or overwrite the
+ * batch buffers).  For parity checks of single points at full size. */
 fk_status fk_get_point_green(const fk_ctx* ctx, int k, double* g, int on_device);
 /* Number of complex64 iterations in the last fk_iterate / fk_iterate_judged. */
 fk_status fk_low_iterations(const fk_ctx* ctx, int* n);

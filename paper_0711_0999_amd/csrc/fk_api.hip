@@ -179,7 +179,7 @@ fk_status set_err(fk_ctx* c, fk_status s, const char* fmt, ...) {
   } while (0)
 
 template <typename T> int batch_cap_for(fk_ctx* c) {
-  const size_t per = sizeof(cplx<T>) * ((size_t)c->ci.n_c + kNBO) * c->ci.n_c +
+  const size_t per = sizeof(cplx<T>) * ((size_t)c->ci.n_c + kBRows) * c->ci.n_c +
                      2 * sizeof(int) * (size_t)c->ci.n_c;
   size_t cap = c->batch_bytes / per;
   if (c->want_batch > 0) cap = (size_t)c->want_batch;
@@ -242,7 +242,15 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }
 
 // Lattice step in precision T (T = double: FP64 path).
+// The batch left by an earlier step and G_loc are stale from here on: both are
+// marked invalid before any device work and valid again only on success.
+void invalidate_results(fk_ctx* c) {
+  c->last_prec = -1;
+  c->have_gloc = false;
+}
+
 template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
+  invalidate_results(c);
   fk_status s = ensure_batch<T>(c);
   if (s != FK_OK) return s;
   Batch<T>& b = lattice_batch<T>(c);
@@ -276,9 +284,6 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
     c->times[6] += elapsed(c->ev[6], c->ev[7]);
   }
   c->times[5] = launches;
-  c->last_nmat = std::min(b.cap, c->npts - (c->npts - 1) / b.cap * b.cap);
-  c->last_k0 = c->npts - c->last_nmat;
-  c->last_prec = sizeof(T) == sizeof(double) ? 0 : 1;
   // non-finite check of G_loc
   HIPCHK(c, fill_u64(c->d_key, 0ULL, 1, c->st));
   HIPCHK(c, launch_maxabs(c->d_gloc, nullptr, (size_t)n * n, c->d_key, c->st));
@@ -287,6 +292,9 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
   if (!(mx <= std::numeric_limits<double>::max()))
     return set_err(c, FK_ENONFINITE, "G_loc has non-finite entries");
   if (ir_out) *ir_out = 0.0;
+  c->last_nmat = std::min(b.cap, c->npts - (c->npts - 1) / b.cap * b.cap);
+  c->last_k0 = c->npts - c->last_nmat;
+  c->last_prec = sizeof(T) == sizeof(double) ? 0 : 1;
   c->have_gloc = true;
   return FK_OK;
 }
@@ -294,11 +302,12 @@ template <typename T> fk_status lattice_step(fk_ctx* c, double* ir_out) {
 // Mixed lattice step: complex64 build and inversion, then ir_steps FP64
 // refinement steps X <- X + X (I - A X), FP64 reduction.
 fk_status lattice_step_mixed(fk_ctx* c, double* ir_out) {
+  invalidate_results(c);
   const int n = c->ci.n_c, ir = c->ir_steps;
   const size_t nn = (size_t)n * n;
   // batch size: complex64 matrix + side buffer, plus three FP64 matrices when
   // refining
-  const size_t per = sizeof(c32) * (nn + (size_t)kNBO * n) + 2 * sizeof(int) * n +
+  const size_t per = sizeof(c32) * (nn + (size_t)kBRows * n) + 2 * sizeof(int) * n +
                      (ir > 0 ? 3 * sizeof(c64) * nn + sizeof(c64) * (n + 1) : 0);
   size_t cap = c->batch_bytes / per;
   if (c->want_batch > 0) cap = (size_t)c->want_batch;
@@ -309,6 +318,7 @@ fk_status lattice_step_mixed(fk_ctx* c, double* ir_out) {
   if (!b.x || b.cap != (int)cap || b.variant != c->variant)
     HIPCHK(c, batch_alloc(b, (int)cap, n, c->variant));
   if (ir > 0 && c->ir_cap != (int)cap) {
+    c->ir_cap = 0;   // counts as allocated only once every buffer is
     c64** bufs[] = {&c->ir_x, &c->ir_p, &c->ir_y};
     for (c64** q : bufs) {
       if (*q) (void)hipFree(*q);
@@ -360,7 +370,10 @@ fk_status lattice_step_mixed(fk_ctx* c, double* ir_out) {
         std::swap(X, Y);
         const double r = read_key(c, &s);
         if (s != FK_OK) return s;
-        if (it == ir - 1) resid = std::max(resid, r);
+        // the last step's residual R = I - A X is that of the iterate entering
+        // it; the returned X + X R has the residual R^2 exactly (Newton), whose
+        // entries are at most N_c max|R|^2: that bound is reported
+        if (it == ir - 1) resid = std::max(resid, (double)n * r * r);
       }
       HIPCHK(c, hipEventRecord(c->ev[3], c->st));
       HIPCHK(c, launch_reduce<double>(X, nn, n, c->d_iota, c->d_iota, 0,
@@ -691,6 +704,7 @@ extern "C" fk_status fk_points(const fk_ctx* c, int* n_points, double* eps,
 extern "C" fk_status fk_set_batch(fk_ctx* c, int batch, int* used) {
   if (!c || batch < 0) return FK_EINVAL;
   c->want_batch = batch;
+  c->last_prec = -1;   // the batch buffers are freed
   batch_free(c->b64);
   batch_free(c->b32);
   fk_status s = ensure_batch<double>(c);
@@ -1038,7 +1052,7 @@ extern "C" fk_status fk_timings(const fk_ctx* c, double* out7) {
 namespace {
 double matrix_bytes(const fk_ctx* c) {
   const double n = c->ci.n_c;
-  return 16.0 * (n * n + kNBO * n) + 8.0 * n;
+  return 16.0 * (n * n + kBRows * n) + 8.0 * n;
 }
 }  // namespace
 
@@ -1048,6 +1062,7 @@ extern "C" fk_status fk_set_tuning(fk_ctx* c, const fk_tuning* t) {
   c->variant = t->tile_rows == 128 ? 1 : 0;
   c->aux.lookahead = t->lookahead != 0;
   if (t->batch > 0) c->want_batch = t->batch;
+  c->last_prec = -1;   // the next step may reallocate the batch
   c->tuned = *t;
   return FK_OK;
 }
@@ -1087,6 +1102,7 @@ extern "C" fk_status fk_autotune(fk_ctx* c, double max_bytes, int keep,
       caps.push_back(b);
   }
   const int n = c->ci.n_c;
+  c->last_prec = -1;   // the trials overwrite and free the batch buffers
   HIPCHK(c, launch_sigma_weight(c->d_sigma, c->d_w, c->d_sigt, n, c->st));
   fk_tuning bestt{64, 1, 0, 0.0, std::numeric_limits<double>::infinity(), 0};
   int trials = 0;

@@ -2,7 +2,8 @@
 // their self-consistency loops together.  Every lattice step of a sweep puts
 // the point matrices of all active instances into uneven batches, so each
 // Gauss-Jordan step is one launch over (instance, point, tile) work items;
-// the impurity updates of all instances share batched inversions too.  The
+// the impurity updates of all instances share one batched inversion (the
+// one-inversion form of the single-instance update).  The
 // sweep is recorded once into a hipGraph and replayed; it is re-recorded when
 // an instance converges and retires.
 #include "fk_ctx.h"
@@ -22,90 +23,13 @@ using namespace fk;
 
 namespace fk {
 
-// Per-instance device view for the batched impurity update.
+// Per-instance device view for the convergence norm.
 struct InstDev {
   c64* gloc;
   c64* gprev;
-  c64* sigma;
-  const c64* w;
-  c64* g0inv;
   int n;
-  double d0, d1, w1;
-  long long s0;      // element offset of the impurity slot
-  int i0;            // int offset of its pivot arrays
   int key;           // slot of this instance in the key array (2 per instance)
 };
-
-__device__ inline c64 cmulw(c64 a, c64 b) {
-  return c64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-
-// Stages of the Falicov-Kimball update in right-weighted form (A -> A W):
-//   0: slot = G_loc W
-//   1: g0inv = inv(slot) + Sigma W
-//   2: slot = C = g0inv + d_c S  (S the point-split delta, d_c = (1 - w1) d1 + w1 d0)
-//   3: Sigma <- (-h S + w1 (1 - w1) (d0 - d1)^2 S inv(C) S) W^-1, key = max
-//      |Sigma change|  (h = (1 - w1) d0 + w1 d1: the inverse of the impurity
-//      Green's function (1 - w1)(g0inv + d0 S)^-1 + w1 (g0inv + d1 S)^-1 is
-//      (g0inv + d1 S) inv(C) (g0inv + d0 S), one inversion instead of three)
-__global__ void k_imp_stage(const InstDev* __restrict__ inst, int stage,
-                            c64* __restrict__ ximp, const int* __restrict__ piv,
-                            const int* __restrict__ rc,
-                            unsigned long long* __restrict__ keys) {
-  const InstDev d = inst[blockIdx.y];
-  const int n = d.n;
-  const size_t total = (size_t)n * n;
-  double mx = 0.0;
-  bool bad = false;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e - (e / n) * n);
-    const c64 wj = d.w[j];
-    if (stage == 0) {
-      ximp[d.s0 + e] = cmulw(d.gloc[e], wj);
-    } else if (stage == 1) {
-      const c64 x0 = ximp[d.s0 + (size_t)piv[d.i0 + i] * n + rc[d.i0 + j]];
-      const c64 sw = cmulw(d.sigma[e], wj);
-      d.g0inv[e] = c64{x0.re + sw.re, x0.im + sw.im};
-    } else if (stage == 2) {
-      double sv = 0.0;
-      if (j == i - 1) sv = 1.0;
-      if (i == 0 && j == n - 1) sv = -1.0;
-      const double dc = (1.0 - d.w1) * d.d1 + d.w1 * d.d0;
-      const c64 g = d.g0inv[e];
-      ximp[d.s0 + e] = c64{g.re + dc * sv, g.im};
-    } else {
-      // (S X S)[i][j] = s_i t_j X[i - 1 mod n][j + 1 mod n], X = inv(C) read
-      // through the pivot maps
-      const int k = (i == 0) ? n - 1 : i - 1, l = (j == n - 1) ? 0 : j + 1;
-      const double gam = d.w1 * (1.0 - d.w1) * (d.d0 - d.d1) * (d.d0 - d.d1);
-      const double h = (1.0 - d.w1) * d.d0 + d.w1 * d.d1;
-      const double sg = gam * ((i == 0) ? -1.0 : 1.0) * ((j == n - 1) ? -1.0 : 1.0);
-      const c64 x = ximp[d.s0 + (size_t)piv[d.i0 + k] * n + rc[d.i0 + l]];
-      c64 df{sg * x.re, sg * x.im};
-      if (j == i - 1) df.re -= h;
-      else if (i == 0 && j == n - 1) df.re += h;
-      const double den = wj.re * wj.re + wj.im * wj.im;
-      const c64 sn{(df.re * wj.re + df.im * wj.im) / den,
-                   (df.im * wj.re - df.re * wj.im) / den};
-      const c64 old = d.sigma[e];
-      const double dr = sn.re - old.re, di = sn.im - old.im;
-      const double a = sqrt(dr * dr + di * di);
-      if (!(a <= 1.79769313486231570815e308)) bad = true;
-      else if (a > mx) mx = a;
-      d.sigma[e] = sn;
-    }
-  }
-  if (stage == 3) {
-    unsigned long long k = bad ? 0x7ff8000000000000ULL
-                               : (unsigned long long)__double_as_longlong(mx);
-    for (int off = 32; off >= 1; off >>= 1) {
-      const unsigned long long o = __shfl_xor(k, off);
-      k = o > k ? o : k;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax(&keys[d.key + 1], k);
-  }
-}
 
 // delta = max |G_loc - G_prev| into keys[key], then G_prev <- G_loc
 __global__ void k_delta(const InstDev* __restrict__ inst,
@@ -160,6 +84,8 @@ struct fk_batch {
   size_t x_cap = 0, b_cap = 0, i_cap = 0, i2_cap = 0;
   c64* xi = nullptr;
   c64* bi = nullptr;
+  std::vector<size_t> imp_s0, imp_i0;   // per active instance: slot offsets
+  std::vector<int> status_inst, status_point;   // per status slot (point -1: impurity)
   int* pivi = nullptr;
   int* rci = nullptr;
   size_t xi_cap = 0, bi_cap = 0, ii_cap = 0, ii2_cap = 0;
@@ -240,7 +166,7 @@ fk_status build_plan(fk_batch* b) {
   for (int id : b->active) {
     const fk_ctx* c = b->inst[id];
     const double n = c->ci.n_c;
-    const double per = 16.0 * (n * n + kNBO * n) + 8.0 * n;
+    const double per = 16.0 * (n * n + kBRows * n) + 8.0 * n;
     for (int k = 0; k < c->npts; ++k) {
       if (used + per > b->chunk_bytes && !groups.back().empty()) {
         groups.emplace_back();
@@ -255,14 +181,18 @@ fk_status build_plan(fk_batch* b) {
   size_t xmax = 0, bmax = 0, imax = 0;
   int status = 0;
   std::vector<std::vector<int>> sizes(groups.size()), sidx(groups.size());
+  b->status_inst.clear();
+  b->status_point.clear();
   for (size_t g = 0; g < groups.size(); ++g) {
     size_t xs = 0, bs = 0, is = 0;
     for (const Job& j : groups[g]) {
       const int n = b->inst[j.inst]->ci.n_c;
       sizes[g].push_back(n);
       sidx[g].push_back(status++);
+      b->status_inst.push_back(j.inst);
+      b->status_point.push_back(j.k);
       xs += (size_t)n * n;
-      bs += (size_t)kNBO * n;
+      bs += (size_t)kBRows * n;
       is += n;
     }
     xmax = std::max(xmax, xs);
@@ -297,8 +227,10 @@ fk_status build_plan(fk_batch* b) {
     const int n = b->inst[b->active[a]]->ci.n_c;
     isz[a] = n;
     isx[a] = status++;
+    b->status_inst.push_back(b->active[a]);
+    b->status_point.push_back(-1);
     xs += (size_t)n * n;
-    bs += (size_t)kNBO * n;
+    bs += (size_t)kBRows * n;
     is += n;
   }
   BCHK(b, grow(&b->xi, &b->xi_cap, xs));
@@ -312,30 +244,20 @@ fk_status build_plan(fk_batch* b) {
   BCHK(b, grow(&b->d_status, &b->status_cap, (size_t)status));
   // instance views
   std::vector<InstDev> iv(na);
+  b->imp_s0.assign(na, 0);
+  b->imp_i0.assign(na, 0);
   size_t so = 0, ioff = 0;
-  std::vector<size_t> s0(na), i0(na);
-  for (int a = 0; a < na; ++a) {
-    const int n = b->inst[b->active[a]]->ci.n_c;
-    s0[a] = so;
-    i0[a] = ioff;
-    so += (size_t)n * n;
-    ioff += n;
-  }
   for (int a = 0; a < na; ++a) {
     fk_ctx* c = b->inst[b->active[a]];
     const int n = c->ci.n_c;
+    b->imp_s0[a] = so;
+    b->imp_i0[a] = ioff;
+    so += (size_t)n * n;
+    ioff += n;
     InstDev& d = iv[a];
     d.gloc = c->d_gloc;
     d.gprev = c->d_gprev;
-    d.sigma = c->d_sigma;
-    d.w = c->d_w;
-    d.g0inv = c->d_g0inv;
     d.n = n;
-    d.d0 = c->m.convention == 0 ? 0.5 * c->m.U : 0.0;
-    d.d1 = c->m.convention == 0 ? -0.5 * c->m.U : -c->m.U;
-    d.w1 = c->m.w1;
-    d.s0 = (long long)s0[a];
-    d.i0 = (int)i0[a];
     d.key = 2 * b->active[a];
   }
   BCHK(b, grow(&b->d_inst, &b->inst_cap, (size_t)std::max(na, 1)));
@@ -345,13 +267,16 @@ fk_status build_plan(fk_batch* b) {
   return FK_OK;
 }
 
-hipError_t launch_imp(fk_batch* b, int stage) {
-  int nmax = 0;
-  for (int id : b->active) nmax = std::max(nmax, b->inst[id]->ci.n_c);
-  int gx = (int)std::min<size_t>(((size_t)nmax * nmax + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_imp_stage, dim3(gx, b->n_active_dev), dim3(256), 0, b->st,
-                     b->d_inst, stage, b->xi, b->pivi, b->rci, b->d_keys);
-  return hipGetLastError();
+// Shifts of the Falicov-Kimball update of one instance (model convention):
+// d0, d1 for the empty and occupied f site, d_c = (1 - w1) d1 + w1 d0, h =
+// (1 - w1) d0 + w1 d1, gam = w1 (1 - w1) (d0 - d1)^2.
+void imp_shifts(const fk_ctx* c, double* dc, double* h, double* gam) {
+  const double d0 = c->m.convention == 0 ? 0.5 * c->m.U : 0.0;
+  const double d1 = c->m.convention == 0 ? -0.5 * c->m.U : -c->m.U;
+  const double w1 = c->m.w1;
+  *dc = (1.0 - w1) * d1 + w1 * d0;
+  *h = (1.0 - w1) * d0 + w1 * d1;
+  *gam = w1 * (1.0 - w1) * (d0 - d1) * (d0 - d1);
 }
 
 // Enqueue one sweep (lattice steps of all active instances, convergence norm,
@@ -403,17 +328,49 @@ hipError_t record_sweep(fk_batch* b) {
   hipLaunchKernelGGL(k_delta, dim3(gx, b->n_active_dev), dim3(256), 0, b->st,
                      b->d_inst, b->d_keys);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // impurity updates, the single-instance form: with X = G_loc W and
+  // Y = Sigma W + d_c S, Sigma_new W = -h S + gam S X (I + Y X)^-1 S; the
+  // matrices I + Y X of all instances share one batched inversion
   const int na = b->n_active_dev;
-  if ((e = launch_imp(b, 0)) != hipSuccess) return e;
+  for (int a = 0; a < na; ++a) {
+    fk_ctx* c = b->inst[b->active[a]];
+    const int n = c->ci.n_c;
+    double dc, h, gam;
+    imp_shifts(c, &dc, &h, &gam);
+    c64* slot = b->xi + b->imp_s0[a];
+    if ((e = launch_right_weight(c->d_gloc, c->d_w, c->d_g0inv, n, n, b->st)) != hipSuccess)
+      return e;
+    if ((e = launch_right_weight(c->d_sigma, c->d_w, c->d_tmp, n, n, b->st)) != hipSuccess)
+      return e;
+    if ((e = launch_bgemm(slot, nullptr, 0.0, c->d_tmp, 0, c->d_g0inv, n, 1, b->st)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_add_identity_shift(slot, n, c->d_g0inv, dc, n, b->st)) != hipSuccess)
+      return e;
+  }
   if ((e = batch_invert<double>(b->impA, na, b->st, b->aux, nullptr, nullptr,
                                 b->d_status)) != hipSuccess)
     return e;
-  if ((e = launch_imp(b, 1)) != hipSuccess) return e;
-  if ((e = launch_imp(b, 2)) != hipSuccess) return e;
-  if ((e = batch_invert<double>(b->impA, na, b->st, b->aux, nullptr, nullptr,
-                                b->d_status)) != hipSuccess)
-    return e;
-  return launch_imp(b, 3);
+  for (int a = 0; a < na; ++a) {
+    const int id = b->active[a];
+    fk_ctx* c = b->inst[id];
+    const int n = c->ci.n_c;
+    double dc, h, gam;
+    imp_shifts(c, &dc, &h, &gam);
+    c64* slot = b->xi + b->imp_s0[a];
+    // (I + Y X)^-1 in natural order, then C^-1 = X (I + Y X)^-1 into the slot
+    if ((e = launch_unpermute<double>(slot, (size_t)n * n, n, b->pivi + b->imp_i0[a],
+                                      b->rci + b->imp_i0[a], n, 1, c->d_tmp, b->st)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_bgemm(slot, nullptr, 0.0, c->d_g0inv, 0, c->d_tmp, n, 1, b->st)) !=
+        hipSuccess)
+      return e;
+    if ((e = launch_sigma_fk(slot, c->d_w, c->d_sigma, n, h, gam, b->d_keys + 2 * id + 1,
+                             b->st)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -526,6 +483,9 @@ extern "C" fk_status fk_batch_iterate(fk_batch* b, int max_sweeps, double tol,
       const fk_status s = build_plan(b);
       if (s != FK_OK) return s;
     }
+    // the active instances' G_loc are rewritten by this sweep: valid again
+    // only once it has succeeded
+    for (int id : b->active) b->inst[id]->have_gloc = false;
     if (use_graph && !b->graph_for_plan) {
       drop_graph(b);
       const auto t0 = std::chrono::steady_clock::now();
@@ -563,10 +523,17 @@ extern "C" fk_status fk_batch_iterate(fk_batch* b, int max_sweeps, double tol,
     b->last_sweep_ms = ms;
     b->total_ms += ms;
     for (int q = 0; q < b->n_status; ++q)
-      if (st[q] != 0)
+      if (st[q] != 0) {
+        const char* what = st[q] > 0 ? "zero pivot" : "non-finite pivot";
+        const int col = (st[q] > 0 ? st[q] : -st[q]) - 1;
+        if (b->status_point[q] >= 0)
+          return berr(b, st[q] > 0 ? FK_ESINGULAR : FK_ENONFINITE,
+                      "sweep %d: instance %d: %s at column %d of matrix %d", sweep + 1,
+                      b->status_inst[q], what, col, b->status_point[q]);
         return berr(b, st[q] > 0 ? FK_ESINGULAR : FK_ENONFINITE,
-                    "sweep %d: inversion %d failed at column %d", sweep + 1, q,
-                    (st[q] > 0 ? st[q] : -st[q]) - 1);
+                    "sweep %d: instance %d: impurity update: %s at column %d",
+                    sweep + 1, b->status_inst[q], what, col);
+      }
     std::vector<int> still;
     for (int id : b->active) {
       b->iters[id]++;

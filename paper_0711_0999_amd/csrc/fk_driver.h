@@ -53,21 +53,22 @@ template <typename T> struct Batch {
   int cap = 0, n = 0, ld = 0;
   size_t stride = 0;
   cplx<T>* x = nullptr;
-  cplx<T>* bbuf = nullptr;     // gathered pivot rows, kNBO x ld per matrix
+  cplx<T>* bbuf = nullptr;     // gathered pivot rows, kBRows x ld per matrix
   int* piv = nullptr;
   int* rowcol = nullptr;
   int* status = nullptr;
   MatDesc* descs = nullptr;
   TileItem* items = nullptr;
-  // per outer step S: tile items of the next block's columns ("narrow") and of
-  // all other columns ("big"), matrix-major so a prefix serves fewer matrices
-  std::vector<int> offN, cntN, offB, cntB;
+  // per outer step S and update phase q (kPhases): tile items, matrix-major
+  // so that a prefix serves fewer matrices (uniform batches: cnt items and
+  // flp algorithmic flops per matrix; uneven: tot items, flp flops in all)
+  std::vector<int> off[kPhases], cnt[kPhases], tot[kPhases];
+  std::vector<double> flp[kPhases];
   int nouter = 0;
   int nmax = 0;       // largest matrix (selects the panel shape)
-  // uneven batches (matrices of different sizes packed back to back): item
-  // totals per step, total pivot ints, and capacities of the buffers
+  // uneven batches (matrices of different sizes packed back to back): total
+  // pivot ints and capacities of the buffers
   bool uniform = true;
-  std::vector<int> totN, totB;
   size_t nints = 0;
   size_t x_cap = 0, b_cap = 0, i_cap = 0, it_cap = 0;
   int d_cap = 0;
@@ -88,34 +89,88 @@ template <typename T> void batch_free(Batch<T>& b) {
   b = Batch<T>();
 }
 
-// Update work items of matrix m for outer step S: pass 0 the next block's
-// column tiles (narrow launch), pass 1 every column tile outside the current
-// and next blocks (big launch).  Items are ordered in bands of kSwz column
-// tiles, rows outer within a band, so the workgroups in flight on one XCD
-// (consecutive items) share both their pivot-block rows and their B columns
-// in its L2.
+// Update work items of matrix m (n rows, tiles of tr_rows rows) for outer
+// step S and phase q, and their algorithmic flops (8 per complex multiply-add:
+// rows x columns x K per tile).  The phases of step S (block_role):
+//   q = 0  single or first block of a pair: the next block's columns, K = block
+//          S; second block: the first block's columns, M = block S (side rows
+//          kNBO..), bringing that block up to date
+//   q = 1  second block: the next block's columns, both blocks' transforms
+//   q = 2  the trailing update of every other column: single block with its
+//          own transform, second block with both (K = 256); nothing for a
+//          first block (delayed until its pair is factored)
+// Items are ordered in bands of kSwz column tiles, rows outer within a band,
+// so the workgroups in flight on one XCD (consecutive items) share both their
+// pivot-block rows and their B columns in its L2.
 constexpr int kSwz = 8;
-inline void push_tiles(std::vector<TileItem>& it, int m, int nt, int ntr, int S,
-                       int pass) {
+inline double push_tiles(std::vector<TileItem>& it, int m, int n, int tr_rows, int S,
+                         int q) {
+  const int nout = (n + kNBO - 1) / kNBO;
+  if (S >= nout) return 0.0;
+  const int role = block_role(n, S);
+  auto width = [&](int blk) { return std::min(kNBO, n - blk * kNBO); };
+  const bool next = S + 1 < nout;
+  int jb = S, kw = width(S), b0 = 0;
+  int lo = 0, hi = -1;        // q < 2: the column blocks [lo, hi] to update
+  int x0 = S, x1 = S + 1;     // q = 2: the column blocks [x0, x1] left out
+  if (q == 0) {
+    if (role == 2) {
+      lo = hi = S - 1;
+      b0 = kNBO;
+    } else if (next) {
+      lo = hi = S + 1;
+    }
+  } else if (q == 1) {
+    if (role == 2 && next) {
+      lo = hi = S + 1;
+      jb = S - 1;
+      kw = width(S - 1) + width(S);
+    }
+  } else {
+    if (role == 1) return 0.0;
+    if (role == 2) {
+      jb = S - 1;
+      kw = width(S - 1) + width(S);
+      x0 = S - 1;
+    }
+  }
+  const int nt = (n + kTile - 1) / kTile, ntr = (n + tr_rows - 1) / tr_rows;
   std::vector<int> cols;
   for (int tc = 0; tc < nt; ++tc) {
     const int blk = tc / (kNBO / kTile);
-    const bool narrow = blk == S + 1;
-    const bool big = blk != S && blk != S + 1;
-    if (pass == 0 ? narrow : big) cols.push_back(tc);
+    const bool take = q < 2 ? (blk >= lo && blk <= hi) : (blk < x0 || blk > x1);
+    if (take) cols.push_back(tc);
   }
+  double flops = 0.0;
   for (size_t c0 = 0; c0 < cols.size(); c0 += kSwz) {
     const size_t c1 = std::min(cols.size(), c0 + kSwz);
     for (int tr = 0; tr < ntr; ++tr)
-      for (size_t c = c0; c < c1; ++c) it.push_back(TileItem{m, (short)tr, (short)cols[c]});
+      for (size_t c = c0; c < c1; ++c) {
+        it.push_back(TileItem{m, (short)tr, (short)cols[c], (short)jb, (short)kw,
+                              (short)b0, 0});
+        flops += 8.0 * std::min(tr_rows, n - tr * tr_rows) *
+                 std::min(kTile, n - cols[c] * kTile) * (double)kw;
+      }
   }
+  return flops;
+}
+
+// Allocate a uniform batch of cap n x n matrices.  On any failure every buffer
+// is released and the batch is left empty (cap 0, x null), so a caller that
+// checks x and cap reallocates instead of launching on a partial batch.
+template <typename T>
+hipError_t batch_alloc_parts(Batch<T>& b, int cap, int n, int variant);
+template <typename T>
+hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
+  const hipError_t e = batch_alloc_parts(b, cap, n, variant);
+  if (e != hipSuccess) batch_free(b);
+  return e;
 }
 
 template <typename T>
-hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
+hipError_t batch_alloc_parts(Batch<T>& b, int cap, int n, int variant) {
   batch_free(b);
   b.variant = variant;
-  b.cap = cap;
   b.n = n;
   b.nmax = n;
   b.ld = n;
@@ -123,7 +178,7 @@ hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
   b.nouter = (n + kNBO - 1) / kNBO;
   hipError_t e;
   if ((e = hipMalloc(&b.x, sizeof(cplx<T>) * b.stride * cap)) != hipSuccess) return e;
-  if ((e = hipMalloc(&b.bbuf, sizeof(cplx<T>) * (size_t)kNBO * b.ld * cap)) != hipSuccess)
+  if ((e = hipMalloc(&b.bbuf, sizeof(cplx<T>) * (size_t)kBRows * b.ld * cap)) != hipSuccess)
     return e;
   if ((e = hipMalloc(&b.piv, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
   if ((e = hipMalloc(&b.rowcol, sizeof(int) * (size_t)n * cap)) != hipSuccess) return e;
@@ -131,7 +186,7 @@ hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
   std::vector<MatDesc> d(cap);
   for (int m = 0; m < cap; ++m) {
     d[m].xoff = (long long)b.stride * m;
-    d[m].boff = (long long)kNBO * b.ld * m;
+    d[m].boff = (long long)kBRows * b.ld * m;
     d[m].n = n;
     d[m].ld = b.ld;
     d[m].ioff = n * m;
@@ -141,31 +196,30 @@ hipError_t batch_alloc(Batch<T>& b, int cap, int n, int variant = 0) {
   if ((e = hipMemcpy(b.descs, d.data(), sizeof(MatDesc) * cap,
                      hipMemcpyHostToDevice)) != hipSuccess)
     return e;
-  const int nt = (n + kTile - 1) / kTile;
-  const int ntr = (n + tile_rows(variant) - 1) / tile_rows(variant);
   std::vector<TileItem> it;
-  b.offN.assign(b.nouter, 0);
-  b.cntN.assign(b.nouter, 0);
-  b.offB.assign(b.nouter, 0);
-  b.cntB.assign(b.nouter, 0);
+  for (int q = 0; q < kPhases; ++q) {
+    b.off[q].assign(b.nouter, 0);
+    b.cnt[q].assign(b.nouter, 0);
+    b.flp[q].assign(b.nouter, 0.0);
+  }
   for (int S = 0; S < b.nouter; ++S) {
-    for (int pass = 0; pass < 2; ++pass) {
-      (pass ? b.offB : b.offN)[S] = (int)it.size();
-      int per = 0;
+    for (int q = 0; q < kPhases; ++q) {
+      b.off[q][S] = (int)it.size();
       for (int m = 0; m < cap; ++m) {
         const size_t before = it.size();
-        push_tiles(it, m, nt, ntr, S, pass);
-        per = (int)(it.size() - before);
+        b.flp[q][S] = push_tiles(it, m, n, tile_rows(variant), S, q);
+        b.cnt[q][S] = (int)(it.size() - before);
       }
-      (pass ? b.cntB : b.cntN)[S] = per;
     }
   }
   if ((e = hipMalloc(&b.items, sizeof(TileItem) * std::max<size_t>(it.size(), 1))) !=
       hipSuccess)
     return e;
-  if (it.empty()) return hipSuccess;
-  return hipMemcpy(b.items, it.data(), sizeof(TileItem) * it.size(),
-                   hipMemcpyHostToDevice);
+  if (!it.empty() && (e = hipMemcpy(b.items, it.data(), sizeof(TileItem) * it.size(),
+                                    hipMemcpyHostToDevice)) != hipSuccess)
+    return e;
+  b.cap = cap;   // complete: only now does the batch count as allocated
+  return hipSuccess;
 }
 
 template <typename P> hipError_t grow(P** ptr, size_t* cap, size_t want) {
@@ -201,7 +255,7 @@ hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
     d[m].ioff = (int)io;
     d[m].status_idx = status_idx[m];
     xo += (size_t)n[m] * n[m];
-    bo += (size_t)kNBO * n[m];
+    bo += (size_t)kBRows * n[m];
     io += (size_t)n[m];
     nouter = std::max(nouter, (n[m] + kNBO - 1) / kNBO);
   }
@@ -224,20 +278,17 @@ hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
                      hipMemcpyHostToDevice)) != hipSuccess)
     return e;
   std::vector<TileItem> it;
-  b.offN.assign(nouter, 0);
-  b.offB.assign(nouter, 0);
-  b.totN.assign(nouter, 0);
-  b.totB.assign(nouter, 0);
+  for (int q = 0; q < kPhases; ++q) {
+    b.off[q].assign(nouter, 0);
+    b.tot[q].assign(nouter, 0);
+    b.flp[q].assign(nouter, 0.0);
+  }
   for (int S = 0; S < nouter; ++S) {
-    for (int pass = 0; pass < 2; ++pass) {
-      (pass ? b.offB : b.offN)[S] = (int)it.size();
-      for (int m = 0; m < nm; ++m) {
-        if (S * kNBO >= n[m]) continue;
-        const int nt = (n[m] + kTile - 1) / kTile;
-        const int ntr = (n[m] + tile_rows(b.variant) - 1) / tile_rows(b.variant);
-        push_tiles(it, m, nt, ntr, S, pass);
-      }
-      (pass ? b.totB : b.totN)[S] = (int)it.size() - (pass ? b.offB : b.offN)[S];
+    for (int q = 0; q < kPhases; ++q) {
+      b.off[q][S] = (int)it.size();
+      for (int m = 0; m < nm; ++m)
+        b.flp[q][S] += push_tiles(it, m, n[m], tile_rows(b.variant), S, q);
+      b.tot[q][S] = (int)it.size() - b.off[q][S];
     }
   }
   if ((e = grow(&b.items, &b.it_cap, it.size())) != hipSuccess) return e;
@@ -246,10 +297,10 @@ hipError_t batch_setup_uneven(Batch<T>& b, const std::vector<int>& n,
                    hipMemcpyHostToDevice);
 }
 
-// Optional timing of the dominant kernel, the trailing update of each outer
-// block ("big" launch): an event pair around every such launch of a uniform
-// batch, with the launch's algorithmic flops, 8 n * cols * K per matrix (n
-// rows, cols outside the two blocks being factored, K the block width).
+// Optional timing of the dominant kernel, the trailing update (phase 2
+// launch): an event pair around every such launch of a uniform batch, with the
+// launch's algorithmic flops, 8 per complex multiply-add (rows x columns x K
+// summed over its tiles).
 struct KernelClock {
   bool on = false;
   std::vector<hipEvent_t> ev;   // event pairs
@@ -300,6 +351,10 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
       hipSuccess)
     return e;
   ++nl;
+  auto items_of = [&](int q, int S, int* count) {
+    *count = b.uniform ? nmat * b.cnt[q][S] : b.tot[q][S];
+    return b.items + b.off[q][S];
+  };
   for (int S = 0; S < b.nouter; ++S) {
     const bool next = S + 1 < b.nouter;
     if ((e = gje_gather<T>(b.x, b.bbuf, b.piv, b.descs, nmat, S, st)) != hipSuccess)
@@ -310,12 +365,19 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
         return e;
       ++nl;
     }
+    // the next block's columns (and, for the second block of a pair, the
+    // first block's columns before them), so that the next panel can start
+    for (int q = 0; q < 2; ++q) {
+      int cnt = 0;
+      const TileItem* it = items_of(q, S, &cnt);
+      if (cnt > 0) {
+        if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, it, cnt, b.variant, st)) !=
+            hipSuccess)
+          return e;
+        ++nl;
+      }
+    }
     if (next) {
-      const int nN = b.uniform ? nmat * b.cntN[S] : b.totN[S];
-      if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offN[S],
-                             nN, S, b.variant, st)) != hipSuccess)
-        return e;
-      ++nl;
       hipStream_t ps = ax.lookahead ? ax.st2 : st;
       if (ax.lookahead) {
         if ((e = hipEventRecord(ax.evN, st)) != hipSuccess) return e;
@@ -327,20 +389,21 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
       ++nl;
       if (ax.lookahead && (e = hipEventRecord(ax.evP, ax.st2)) != hipSuccess) return e;
     }
-    const int nB = b.uniform ? nmat * b.cntB[S] : b.totB[S];
-    KernelClock* ck = (ax.clk && b.uniform && nB > 0 &&
-                       ax.clk->used + 2 <= (int)ax.clk->ev.size()) ? ax.clk : nullptr;
-    if (ck && (e = hipEventRecord(ck->ev[ck->used], st)) != hipSuccess) return e;
-    if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, b.items + b.offB[S],
-                           nB, S, b.variant, st)) != hipSuccess)
-      return e;
-    ++nl;
-    if (ck) {
-      if ((e = hipEventRecord(ck->ev[ck->used + 1], st)) != hipSuccess) return e;
-      const double n = b.n, K = std::min(kNBO, b.n - S * kNBO);
-      const double k1 = next ? std::min(kNBO, b.n - (S + 1) * kNBO) : 0;
-      ck->flops.push_back(8.0 * n * (n - K - k1) * K * nmat);
-      ck->used += 2;
+    int nB = 0;
+    const TileItem* itB = items_of(2, S, &nB);
+    if (nB > 0) {
+      KernelClock* ck = (ax.clk && b.uniform &&
+                         ax.clk->used + 2 <= (int)ax.clk->ev.size()) ? ax.clk : nullptr;
+      if (ck && (e = hipEventRecord(ck->ev[ck->used], st)) != hipSuccess) return e;
+      if ((e = gje_update<T>(b.x, b.bbuf, b.rowcol, b.descs, itB, nB, b.variant, st)) !=
+          hipSuccess)
+        return e;
+      ++nl;
+      if (ck) {
+        if ((e = hipEventRecord(ck->ev[ck->used + 1], st)) != hipSuccess) return e;
+        ck->flops.push_back(b.flp[2][S] * nmat);
+        ck->used += 2;
+      }
     }
     if (next && ax.lookahead && (e = hipStreamWaitEvent(st, ax.evP, 0)) != hipSuccess)
       return e;

@@ -14,14 +14,18 @@
 //           the quarter's (half's) transform on the matrix cores.
 //   gather  copies the pivot rows of the step into a side buffer B (their
 //           values before the step outside the block, the block's inverse
-//           pivot submatrix inside it).
+//           pivot submatrix inside it); B holds the rows of two blocks.
 //   fix     the block's columns of the J0 rows pivoted earlier, from that
 //           inverse (one small product per row tile).  The block now holds
 //           the transformed identity columns M = E[:, P] of all elementary
 //           Gauss-Jordan transforms of the step.
-//   update  every other column tile: C <- mask_P(C) + M B (K = 128), a batched
-//           complex GEMM on the matrix cores (three real products per complex
-//           one), double-buffered K chunks in LDS, two workgroups per CU.
+//   update  every other column tile: C <- mask_P(C) + M B, a batched complex
+//           GEMM on the matrix cores (three real products per complex one),
+//           double-buffered K chunks in LDS, two workgroups per CU.  Blocks
+//           are applied in pairs (K = 256, see block_role): the first block
+//           of a pair updates only the next block's columns, the second
+//           brings the first block's columns up to date and then applies both
+//           transforms to all other columns at once.
 // The host runs the update of the next block's columns first; with the
 // look-ahead schedule it factors that block on a second stream while the big
 // update of the current step runs.
@@ -540,7 +544,7 @@ __global__ void k_gather(const cplx<T>* __restrict__ xbuf,
   if (J0 >= d.n || l >= min(kNBO, d.n - J0)) return;
   const int p = pivbuf[d.ioff + J0 + l];
   const cplx<T>* src = xbuf + d.xoff + (size_t)p * d.ld;
-  cplx<T>* dst = bbuf + d.boff + (size_t)l * d.ld;
+  cplx<T>* dst = bbuf + d.boff + (size_t)(block_brow(d.n, S) + l) * d.ld;
   for (int c = threadIdx.x; c < d.n; c += blockDim.x) dst[c] = src[c];
 }
 
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(512, 1) void k_fix(
   const int wO = min(kNBO, n - J0);
   const int nch = (wO + kKC - 1) / kKC;
   cplx<T>* xm = xbuf + d.xoff;
-  const cplx<T>* bm = bbuf + d.boff;
+  const cplx<T>* bm = bbuf + d.boff + (size_t)block_brow(n, S) * ld;
   const int* piv = pivbuf + d.ioff;
 
   const int tid = threadIdx.x;
@@ -700,7 +704,7 @@ template <typename T, int WR>
 __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
     cplx<T>* __restrict__ xbuf, const cplx<T>* __restrict__ bbuf,
     const int* __restrict__ rowcolbuf, const MatDesc* __restrict__ descs,
-    const TileItem* __restrict__ items, int nitems, int S) {
+    const TileItem* __restrict__ items, int nitems) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int TR = 32 * WR, NT = 128 * WR;
   constexpr int AP = kKC + 1, BP = kTile + 1;
@@ -722,11 +726,12 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
     const TileItem ti = items[it];
     const MatDesc d = descs[ti.mat];
     const int n = d.n, ld = d.ld;
-    const int J0 = S * kNBO, wO = min(kNBO, n - J0);
+    // M = columns [J0, J0 + wO), B = side-buffer rows [b0, b0 + wO)
+    const int J0 = ti.jb * kNBO, wO = ti.kw;
     const int nch = (wO + kKC - 1) / kKC;
     const int r0 = ti.tr * TR, c0 = ti.tc * kTile;
     cplx<T>* xm = xbuf + d.xoff;
-    const cplx<T>* bm = bbuf + d.boff;
+    const cplx<T>* bm = bbuf + d.boff + (size_t)ti.b0 * ld;
     const int* rowcol = rowcolbuf + d.ioff;
 
     // pivot-row mask (the C tile itself is read during the last K chunk and
@@ -936,17 +941,17 @@ hipError_t gje_fix(cplx<T>* x, const cplx<T>* bbuf, const int* piv,
 template <typename T>
 hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
                       const MatDesc* d, const TileItem* items, int nitems,
-                      int S, int variant, hipStream_t st) {
+                      int variant, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   // one workgroup per item (a persistent grid of two workgroups per CU
   // measured 4% slower: the dispatcher already overlaps the tiles' prologues)
   const int grid = 8 * ((nitems + 7) / 8);
   if (variant == 1)
     hipLaunchKernelGGL((k_update<T, 4>), dim3(grid), dim3(512), 0, st, x, bbuf,
-                       rowcol, d, items, nitems, S);
+                       rowcol, d, items, nitems);
   else
     hipLaunchKernelGGL((k_update<T, 2>), dim3(grid), dim3(256), 0, st, x, bbuf,
-                       rowcol, d, items, nitems, S);
+                       rowcol, d, items, nitems);
   return hipGetLastError();
 }
 
@@ -959,7 +964,7 @@ hipError_t gje_update(cplx<T>* x, const cplx<T>* bbuf, const int* rowcol,
                                  const MatDesc*, int, int, hipStream_t);      \
   template hipError_t gje_update<T>(cplx<T>*, const cplx<T>*, const int*,     \
                                     const MatDesc*, const TileItem*, int, int, \
-                                    int, hipStream_t);
+                                    hipStream_t);
 FK_INST(double)
 FK_INST(float)
 

@@ -4,7 +4,7 @@ single-instance runs and the oracle."""
 import numpy as np
 import pytest
 
-from oracle import dmft
+from oracle import dmft, impurity
 
 pytestmark = pytest.mark.gpu
 
@@ -109,3 +109,68 @@ def test_batch_mixing_small_and_long_contours(lib):
                                    e_field=kw["E"], n_eps=kw["n_eps"],
                                    n_ebar=kw["n_ebar"]), 2)
         assert relerr(b.instance(0).get_gloc(), ro["gloc"]) < 1e-10
+
+
+# C4-sized uneven instances (t_min = -10, dtau = dt, beta = 10, as the C4
+# sweep): N_c = 500, 1050 and 750, with small rules so the oracle stays quick
+C4_SIZED = [
+    dict(t_min=-10.0, t_max=10.0, dt=0.1, dtau=0.1, beta=10.0, U=1.3, E=2.2,
+         n_eps=5, n_ebar=5),
+    dict(t_min=-10.0, t_max=20.0, dt=1.0 / 15.0, dtau=1.0 / 15.0, beta=10.0, U=0.7,
+         E=0.9, n_eps=3, n_ebar=3),
+    dict(t_min=-10.0, t_max=10.0, dt=1.0 / 15.0, dtau=1.0 / 15.0, beta=10.0, U=2.1,
+         E=3.4, n_eps=3, n_ebar=4),
+]
+
+
+def test_c4_sized_batch_every_instance_against_oracle(lib):
+    """Two replayed sweeps from Sigma = 0 give each instance a physical Sigma;
+    the third sweep (lattice steps of all instances in shared uneven chunks,
+    then the batched impurity updates) is checked for every instance against
+    the oracle's lattice step and impurity update from that same Sigma:
+    G_loc, j(t) and the new Sigma within 1e-10.  The odd (N_c = 1050, 9
+    blocks) and even (500, 750: 4 and 6 blocks) block counts follow different
+    pairings of the blocks within the same launches."""
+    print("case: C4-sized batch, N_c = 500 / 1050 / 750, every instance", flush=True)
+    with lib.Batch(C4_SIZED) as b:
+        assert [b.instance(i).n_c for i in range(3)] == [500, 1050, 750]
+        b.set_chunk_bytes(60e6)      # several chunks, instances split across them
+        b.iterate(2, tol=0.0, use_graph=True)
+        sig = [b.instance(i).get_sigma() for i in range(3)]
+        r = b.iterate(1, tol=0.0, use_graph=True)
+        assert list(r["iters"]) == [3, 3, 3]
+        for i, kw in enumerate(C4_SIZED):
+            v = b.instance(i)
+            print(f"  instance {i}: oracle, N_c = {v.n_c}", flush=True)
+            p = dmft.Problem(t_min=kw["t_min"], t_max=kw["t_max"], dt=kw["dt"],
+                             dtau=kw["dtau"], beta=kw["beta"], u=kw["U"],
+                             e_field=kw["E"], n_eps=kw["n_eps"], n_ebar=kw["n_ebar"])
+            go, jo, _ = dmft.lattice_only(p, sig[i])
+            g = v.get_gloc()
+            assert np.max(np.abs(sig[i])) > 0.01
+            assert relerr(g, go) < 1e-10, i
+            assert relerr(v.get_current()[1], jo) < 1e-10, i
+            z, wts = v.contour_points()
+            # the oracle's sequence in long double (its complex128 rounding
+            # reaches 7e-10 of max|Sigma| at N_c = 1050)
+            ref = impurity.update_extended(g, sig[i], wts, 0.0, kw["U"], 0.5)
+            assert relerr(v.get_sigma(), ref) < 1e-10, i
+
+
+def test_batch_zero_pivot_names_instance_and_point(lib):
+    """An exactly singular point matrix in one instance of a sweep: FK_ESINGULAR
+    naming the instance, the point and the column (the construction of the
+    single-context test: 3 x 3 rule, point 4 has eps = ebar = 0, Sigma cancels
+    column 5 of its G0^-1 exactly)."""
+    print("case: batch with an exactly singular point matrix", flush=True)
+    kw = dict(t_min=-2.0, t_max=2.0, dt=0.5, dtau=0.5, beta=2.0, U=1.0, E=1.0,
+              n_eps=3, n_ebar=3)
+    with lib.Batch([INSTANCES[0], kw]) as b:
+        v = b.instance(1)
+        s = np.zeros((v.n_c, v.n_c), np.complex128)
+        s[5, 5], s[6, 5] = 4j, -4j            # (i, -i) / dt^2 with dt = 0.5
+        v.set_sigma(s)
+        with pytest.raises(lib.FkError) as err:
+            b.iterate(1, tol=0.0, use_graph=False)
+        assert err.value.status == lib.FK_ESINGULAR
+        assert "instance 1: zero pivot at column 5 of matrix 4" in str(err.value), str(err.value)

@@ -8,13 +8,24 @@ benchmark times (batches of 757 points, 64-row update tiles, no look-ahead).
 - A property at full size: with U = 0 the whole 3025-point step gives the
   Bloch current j(t) = -K sin(E t) theta(t), K = sum_a w_a x_a f(x_a), and
   n(t) = 1/2, independently of the oracle.
+- From a physical Sigma (the GPU's Sigma after two FP64 iterations of the C2
+  workload from Sigma = 0, fed to both sides): sampled G_k of the full
+  3025-point step, the impurity update of the full step's G_loc, and the whole
+  G_loc and j(t) of a 3 x 3 rule on the same N_c = 1800 contour (eqs. g_loc,
+  effective_medium, g_imp_solve).  The same impurity parity at N_c = 4100 (the
+  long contour, Sigma after two iterations of a 3 x 3 rule).
+- The impurity update is compared with the oracle's sequence evaluated in long
+  double (impurity.update_extended): in complex128 that sequence's final
+  Dyson subtraction (two matrices of order 1/dt leaving one of order Sigma)
+  costs it up to 7e-10 of max|Sigma| at these sizes, above the bar; the
+  long-double evaluation of the same steps stays near 1e-13.
 """
 import math
 
 import numpy as np
 import pytest
 
-from oracle import dmft, lattice
+from oracle import dmft, impurity, lattice
 from paper_0711_0999_amd import configs, inputs
 
 pytestmark = pytest.mark.gpu
@@ -66,3 +77,103 @@ def test_c2_u0_bloch_current_full_size(lib):
     kin = float(np.sum(wa * x / (1.0 + np.exp(10.0 * x))))
     assert np.max(np.abs(j - np.where(t > 0, -kin * np.sin(t), 0.0))) < 1e-11
     assert np.max(np.abs(n - 0.5)) < 1e-11
+
+
+def problem_of(w, **over):
+    d = dict(t_min=w.t_min, t_max=w.t_max, dt=w.dt, dtau=w.dtau, beta=w.beta,
+             u=w.U, e_field=w.E, n_eps=w.n_eps, n_ebar=w.n_ebar)
+    d.update(over)
+    return dmft.Problem(**d)
+
+
+@pytest.fixture(scope="module")
+def c2_physical(lib):
+    """Two FP64 iterations of C2 at U = 1 (55 x 55 points, from Sigma = 0) in
+    the benchmark's launch configuration, then a third lattice step and
+    impurity update from the resulting Sigma: that Sigma, the step's G_loc and
+    sampled G_k of its last batch, and the updated Sigma."""
+    w = configs.c2(1.0)
+    print("case: C2 full size, physical Sigma (two iterations)", flush=True)
+    with lib.Context(**w.kwargs()) as ctx:
+        bench_config(ctx)
+        ctx.iterate(2, tol=0.0)
+        sig = ctx.get_sigma()
+        ctx.compute_gloc()
+        first = 3 * 757
+        ks = [first, first + 1 + int(inputs.sample_points(700, 1, seed=23)[0]), 3024]
+        gks = {k: ctx.get_point_green(k) for k in ks}
+        gloc = ctx.get_gloc()
+        ctx.impurity_update()
+        sig_new = ctx.get_sigma()
+        z, wts = ctx.contour_points()
+    return dict(w=w, sigma=sig, gloc=gloc, gks=gks, sigma_new=sig_new, wts=wts)
+
+
+def test_c2_physical_sigma_sampled_points(c2_physical):
+    d = c2_physical
+    w = d["w"]
+    z, wts, n_t, eps, ebar, rho = problem_of(w).grid()
+    st = lattice.weighted_sigma(d["sigma"], wts)
+    assert np.max(np.abs(d["sigma"])) > 0.05       # a Sigma of the interacting problem
+    for k, g in d["gks"].items():
+        print(f"  point {k}: eps {eps[k]:.3f} ebar {ebar[k]:.3f}", flush=True)
+        go = lattice.point_green(z, n_t, w.E, 0.0, w.beta, eps[k], ebar[k], st)
+        assert relerr(g, go) < 1e-10, k
+
+
+def test_c2_impurity_update_full_size(c2_physical):
+    """The impurity update of the full 3025-point step's G_loc (one inversion
+    on the device, the paper's four in the oracle)."""
+    d = c2_physical
+    w = d["w"]
+    print("  oracle impurity update at N_c = 1800 (long double)", flush=True)
+    ref = impurity.update_extended(d["gloc"], d["sigma"], d["wts"], 0.0, w.U, w.w1)
+    assert relerr(d["sigma_new"], ref) < 1e-10
+
+
+def test_c2_contour_whole_gloc_and_current(lib, c2_physical):
+    """The whole G_loc (all 1800^2 entries) and j(t) of a 3 x 3 rule on the C2
+    contour from the physical Sigma, then the impurity update, against the
+    oracle."""
+    d = c2_physical
+    w = d["w"]
+    print("case: C2 contour, 3 x 3 points, whole G_loc from the physical Sigma",
+          flush=True)
+    kw = dict(w.kwargs(), n_eps=3, n_ebar=3)
+    with lib.Context(**kw) as ctx:
+        ctx.set_sigma(d["sigma"])
+        ctx.compute_gloc()
+        g = ctx.get_gloc()
+        j = ctx.get_current()[1]
+        ctx.impurity_update()
+        s_new = ctx.get_sigma()
+    print("  oracle lattice step, 9 points at N_c = 1800", flush=True)
+    go, jo, _ = dmft.lattice_only(problem_of(w, n_eps=3, n_ebar=3), d["sigma"])
+    assert relerr(g, go) < 1e-10
+    assert relerr(j, jo) < 1e-10
+    print("  oracle impurity update at N_c = 1800 (long double)", flush=True)
+    ref = impurity.update_extended(g, d["sigma"], d["wts"], 0.0, w.U, w.w1)
+    assert relerr(s_new, ref) < 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_long_contour_impurity_update(lib):
+    """N_c = 4100 (t in [-5, 195], dt = dtau = 0.1): Sigma after two FP64
+    iterations of a 3 x 3 rule at U = 1, E = 2, then one more lattice step and
+    impurity update, against the oracle's update of the same G_loc and Sigma."""
+    w = configs.long_contour(1.0, 2.0)
+    print("case: N_c = 4100, impurity update from a physical Sigma", flush=True)
+    kw = dict(w.kwargs(), n_eps=3, n_ebar=3)
+    with lib.Context(**kw) as ctx:
+        assert ctx.n_c == 4100
+        ctx.iterate(2, tol=0.0)
+        sig = ctx.get_sigma()
+        ctx.compute_gloc()
+        g = ctx.get_gloc()
+        ctx.impurity_update()
+        s_new = ctx.get_sigma()
+        z, wts = ctx.contour_points()
+    assert np.max(np.abs(sig)) > 0.05
+    print("  oracle impurity update at N_c = 4100 (long double, minutes)", flush=True)
+    ref = impurity.update_extended(g, sig, wts, 0.0, w.U, w.w1)
+    assert relerr(s_new, ref) < 1e-10

@@ -218,3 +218,92 @@ def test_averaged_quadrature_lattice_step(lib):
     assert relerr(ctx.get_gloc(), go) < TOL64
     assert relerr(ctx.get_current()[1], jo) < TOL64
     ctx.close()
+
+
+def _singular_sigma(n_c, col, dt):
+    """Sigma whose weighted form W Sigma W equals column `col` of G0_k^-1 at the
+    point eps = ebar = 0 (mu = 0), so that A_k = G0_k^-1 - W Sigma W has an
+    exactly zero column there.  At that point G0_k^-1 = i (I - P + e_0
+    e_{N-1}^T) exactly (every phase and the Fermi factor are trivial), so the
+    column holds i on the diagonal and -i just below it; with an upper-branch
+    column and dt a power of two, Sigma = (i, -i) / dt^2 is exact in binary
+    and so is W Sigma W."""
+    s = np.zeros((n_c, n_c), np.complex128)
+    s[col, col] = 1j / dt ** 2
+    s[col + 1, col] = -1j / dt ** 2
+    return s
+
+
+@pytest.mark.parametrize("batch", [0, 2])
+def test_zero_pivot_reports_the_point(lib, batch):
+    """The error contract of the lattice step: a point matrix that is exactly
+    singular gives FK_ESINGULAR naming its point index and column, every kernel
+    still exits normally (the zero pivot only sets a status flag), and the
+    context stays usable.  3 x 3 rule: the middle node is 0, so point
+    k = 1 * 3 + 1 = 4 has eps = ebar = 0.  The column lies where the field is
+    on (t = 0.5, 1.0), so the band phase between its two rows is nonzero for
+    every other point (eps da or ebar dg) and only point 4 is singular (a
+    column at t <= 0 would make every eps = 0 point singular, ebar dg = 0
+    there)."""
+    say(f"case: exactly singular point matrix, batch={batch}")
+    kw = dict(t_min=-2.0, t_max=2.0, dt=0.5, dtau=0.5, beta=2.0, U=1.0, E=1.0,
+              n_eps=3, n_ebar=3)
+    ctx = lib.Context(**kw)
+    assert ctx.n_c == 20
+    e, eb, _ = ctx.points()
+    assert e[4] == 0.0 and eb[4] == 0.0
+    if batch:
+        ctx.set_batch(batch)
+    col = 5                        # rows 5, 6: t = 0.5, 1.0 on the upper branch
+    ctx.set_sigma(_singular_sigma(ctx.n_c, col, 0.5))
+    with pytest.raises(lib.FkError) as err:
+        ctx.compute_gloc()
+    assert err.value.status == lib.FK_ESINGULAR
+    msg = str(err.value)
+    assert f"zero pivot at column {col} of matrix 4" in msg, msg
+    # no G_loc after a failed step
+    with pytest.raises(lib.FkError) as err:
+        ctx.get_gloc()
+    assert err.value.status == lib.FK_ESTATE
+    with pytest.raises(lib.FkError) as err:
+        ctx.impurity_update()
+    assert err.value.status == lib.FK_ESTATE
+    # usable afterwards, and right
+    sig = inputs.random_sigma(ctx.n_c, seed=31, scale=0.05)
+    ctx.set_sigma(sig)
+    ctx.compute_gloc()
+    p = dmft.Problem(t_min=-2.0, t_max=2.0, dt=0.5, dtau=0.5, beta=2.0, u=1.0,
+                     e_field=1.0, n_eps=3, n_ebar=3)
+    go, _, _ = dmft.lattice_only(p, sig)
+    assert relerr(ctx.get_gloc(), go) < TOL64
+    ctx.close()
+
+
+def test_point_green_is_refused_after_the_batch_changes(lib):
+    """fk_get_point_green reads the batch buffers of the last FP64 step; after
+    fk_set_batch (buffers freed and reallocated), fk_set_tuning, a mixed step
+    or a failed step it must refuse with FK_ESTATE before any device read."""
+    say("case: point Green's function after the batch changes")
+    kw = dict(t_min=-1.0, t_max=2.0, dt=0.1, dtau=0.1, beta=1.3, U=1.0, E=1.5,
+              n_eps=3, n_ebar=4)
+    ctx = lib.Context(**kw)
+    ctx.set_sigma(inputs.random_sigma(ctx.n_c, seed=32, scale=0.1))
+    ctx.compute_gloc()
+    ctx.get_point_green(11)                      # last point: in the last batch
+    ctx.set_batch(3)
+    with pytest.raises(lib.FkError) as err:
+        ctx.get_point_green(11)
+    assert err.value.status == lib.FK_ESTATE
+    ctx.compute_gloc()
+    ctx.get_point_green(11)
+    ctx.set_tuning(tile_rows=128, batch=3, lookahead=0)
+    with pytest.raises(lib.FkError) as err:
+        ctx.get_point_green(11)
+    assert err.value.status == lib.FK_ESTATE
+    ctx.compute_gloc()
+    ctx.get_point_green(11)
+    ctx.compute_gloc(lib.FK_MIXED)
+    with pytest.raises(lib.FkError) as err:
+        ctx.get_point_green(11)
+    assert err.value.status == lib.FK_ESTATE
+    ctx.close()
