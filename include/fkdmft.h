@@ -168,6 +168,18 @@ fk_status fk_get_zeroth_moment(const fk_ctx* ctx, double* m0);
  * lattice step. */
 fk_status fk_wigner_dos(const fk_ctx* ctx, int n_T, const int* t_index, int n_w,
                         const double* omega, double* dos);
+/* fk_wigner_dos for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, result and errors, but the time indices, frequencies and
+ * result are staged through a 4 MiB static device array of the library (one
+ * per GPU, set up by fk_create, held until the process ends) instead of a
+ * per-call allocation; no hipMalloc, hipFree or allocating library call.
+ * 256-byte-aligned segments of 4 n_T + 8 n_w + 8 n_T n_w bytes must fit in
+ * 4 MiB, else FK_EINVAL (e.g. 100 times x 5000 frequencies fit).  All calls on
+ * one GPU share the array: calls that overlap in time on the same GPU (other
+ * threads or streams) race; serialize them. */
+fk_status fk_wigner_dos_noalloc(const fk_ctx* ctx, int n_T, const int* t_index,
+                                int n_w, const double* omega, double* dos);
 /* Equal-time spectral moments of the local retarded function (Sec. II, moments
  * paragraph) at T = t_min + i dt, i = t_index[r] (3 <= i <= N_t - 4): with
  * f(s) = G^R(T + s/2, T - s/2), mu0 = i f(0), mu1 = -f'(0), mu2 = -i f''(0)

@@ -14,10 +14,47 @@
 
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace fk;
+
+// ============================================================ static scratch
+// Staging memory of fk_wigner_dos_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never passes the array's
+// name to a kernel or a copy (on the host it only stands in for the symbol):
+// its device address is looked up once per device with hipGetSymbolAddress
+// while that device is current (fk_create) and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Look up this device's scratch address once (dev must be current).
+hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[dev] = e;
+    g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  return g_scratch_err[dev];
+}
+
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_done[dev] ? g_scratch_ptr[dev] : nullptr;
+}
+}  // namespace
 
 // ===================================================================== host ==
 namespace {
@@ -526,8 +563,12 @@ extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
     return FK_EINVAL;
   if (ci.n_c > kMaxN || ci.n_c < 3) return FK_EINVAL;
 
-  int ndev = 0;
+  int ndev = 0, dev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return FK_EDEVICE;
+  if (hipGetDevice(&dev) != hipSuccess) return FK_EDEVICE;
+  // the no-allocation entry point's staging array on this device (its
+  // failure only disables fk_wigner_dos_noalloc, which then reports it)
+  (void)scratch_setup(dev);
 
   fk_ctx* c = new (std::nothrow) fk_ctx();
   if (!c) return FK_ENOMEM;
@@ -535,6 +576,7 @@ extern "C" fk_status fk_create(const fk_contour* cont, const fk_model* mod,
   c->c = *cont;
   c->m = *mod;
   c->ci = ci;
+  c->dev = dev;
   const int n = ci.n_c, n_t = ci.n_t;
 
   // quadrature points k = a * n_ebar + b of the n_eps x n_ebar product rule;
@@ -820,6 +862,42 @@ extern "C" fk_status fk_wigner_dos(const fk_ctx* cc, int n_T, const int* t_index
   CallBuffer buf;
   HIPCHK(c, hipMalloc(&buf.p, off_o + bo));
   char* base = static_cast<char*>(buf.p);
+  HIPCHK(c, hipMemcpyAsync(base, t_index, bi, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(base + off_w, omega, bw, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, launch_wigner_dos(c->d_gloc, n_t, n, c->c.dt, reinterpret_cast<int*>(base),
+                              n_T, reinterpret_cast<double*>(base + off_w), n_w,
+                              reinterpret_cast<double*>(base + off_o), c->st));
+  HIPCHK(c, hipMemcpyAsync(dos, base + off_o, bo, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return FK_OK;
+}
+
+extern "C" fk_status fk_wigner_dos_noalloc(const fk_ctx* cc, int n_T, const int* t_index,
+                                           int n_w, const double* omega, double* dos) {
+  fk_ctx* c = const_cast<fk_ctx*>(cc);
+  if (!c || !t_index || !omega || !dos || n_T < 1 || n_w < 1) return FK_EINVAL;
+  const int n_t = c->ci.n_t, n = c->ci.n_c;
+  for (int r = 0; r < n_T; ++r)
+    if (t_index[r] < 0 || t_index[r] >= n_t)
+      return set_err(c, FK_EINVAL, "time index %d outside [0, N_t)", t_index[r]);
+  for (int q = 0; q < n_w; ++q)
+    if (!std::isfinite(omega[q])) return set_err(c, FK_EINVAL, "non-finite frequency");
+  // staging layout in the static array: time indices, frequencies, result,
+  // each segment 256-byte aligned
+  const size_t bi = sizeof(int) * (size_t)n_T, bw = sizeof(double) * (size_t)n_w;
+  const size_t bo = sizeof(double) * (size_t)n_T * n_w;
+  const size_t off_w = (bi + 255) / 256 * 256, off_o = off_w + (bw + 255) / 256 * 256;
+  if (off_o + bo > kScratchBytes)
+    return set_err(c, FK_EINVAL,
+                   "fk_wigner_dos_noalloc: %d times x %d frequencies need %zu bytes of "
+                   "staging, above its %zu-byte static scratch", n_T, n_w, off_o + bo,
+                   kScratchBytes);
+  if (!c->have_gloc) return set_err(c, FK_ESTATE, "no lattice step yet");
+  unsigned char* base = static_cast<unsigned char*>(scratch_ptr(c->dev));
+  if (!base)
+    return set_err(c, FK_EDEVICE, "static scratch of device %d unavailable: %s", c->dev,
+                   hipGetErrorString(c->dev >= 0 && c->dev < kMaxDevices
+                                         ? g_scratch_err[c->dev] : hipErrorInvalidDevice));
   HIPCHK(c, hipMemcpyAsync(base, t_index, bi, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(base + off_w, omega, bw, hipMemcpyHostToDevice, c->st));
   HIPCHK(c, launch_wigner_dos(c->d_gloc, n_t, n, c->c.dt, reinterpret_cast<int*>(base),

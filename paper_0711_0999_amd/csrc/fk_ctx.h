@@ -24,6 +24,7 @@ struct fk_ctx {
   std::vector<double> eps, ebar, rho;
   hipStream_t st = nullptr;
   bool own_stream = false;
+  int dev = 0;                     // HIP device of the context
   std::string err;
 
   // device

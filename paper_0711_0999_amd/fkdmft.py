@@ -87,6 +87,7 @@ SIGNATURES = {
     "fk_get_zeroth_moment": (ctypes.c_int, [_vp, _dp]),
     "fk_wigner_dos": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _dp, _dp]),
     "fk_equal_time_moments": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _dp]),
+    "fk_wigner_dos_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _dp, _dp]),
     "fk_get_point_green": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int]),
     "fk_set_kernel_clock": (ctypes.c_int, [_vp, ctypes.c_int]),
     "fk_kernel_clock": (ctypes.c_int, [_vp, _dp]),
@@ -312,6 +313,17 @@ class Context:
         out = np.zeros((len(ti), len(om)))
         self._check(self._lib.fk_wigner_dos(self._h, len(ti), ti.ctypes.data, len(om),
                                             _dptr(om), _dptr(out)), "fk_wigner_dos")
+        return out
+
+    def wigner_dos_noalloc(self, t_index, omega):
+        """wigner_dos staged through the library's static device array (no
+        device allocation in the call)."""
+        ti = np.ascontiguousarray(t_index, dtype=np.int32)
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        out = np.zeros((len(ti), len(om)))
+        self._check(self._lib.fk_wigner_dos_noalloc(self._h, len(ti), ti.ctypes.data,
+                                                    len(om), _dptr(om), _dptr(out)),
+                    "fk_wigner_dos_noalloc")
         return out
 
     def moments(self, t_index):
