@@ -8,8 +8,17 @@ Inputs are the physical parameters only (synthetic, resident on the device).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--U 1.0]
                 [--mixed] [--converge | --no-converge] [--no-cpu-baseline]
-                [--workload c2|c1]
+                [--workload c2|c1|long|c4|c2-converge]
 Prints ONE JSON line.
+
+--workload c2-converge [--Us 0.5 1 1.5 2] [--forms fp64 switch warm]
+    [--weights W.npz]: the headline loop on the full C2 grid, to
+    delta < 1e-8 from Sigma = 0 (fp64: plain FP64; switch: complex64 steps
+    then FP64), and from the network's judged proposal on the converged Sigma
+    of E - 0.25 (warm: the switching loop started there); seconds, iterations
+    and the fraction of the matrix-core peak.
+--workload c4 [--tol 1e-8] [--max-sweeps 80]: the 32-instance uneven sweep
+    (hipGraph replay) to convergence with retirement.
 """
 import argparse
 import json
@@ -24,13 +33,18 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel (the big trailing update,
+# HBM bytes per launch of the dominant kernel (the trailing update,
 # fk::k_update<double, 2>, 757-matrix batches of the C2 workload), from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs summarized under profiles/, each
-# scaled by the same counter's reading for a plain 256 MiB copy (FETCH_SIZE x
-# 2.00, WRITE_SIZE x 1.00).  Reported only for that kernel and batch size.
-PROFILED_TRAFFIC = {"kernel": "fk::k_update<double, 2>", "batch": 757,
-                    "bytes_per_launch": 82.58e9}
+# scaled by the same counter's reading for a plain 256 MiB copy.  Reported only
+# for that kernel, batch size and schedule ("paired": K = 256 updates); None
+# until the counters have been taken on the current kernel.
+PROFILED_TRAFFIC = None
+
+# Each complex product of the trailing update is formed from three real ones
+# (Gauss), so its matrix cores execute 6 of the 8 real flops per complex
+# multiply-add that the algorithmic count credits.
+EXECUTED_PER_ALGORITHMIC = 0.75
 
 
 def log(*a):
@@ -77,14 +91,55 @@ def sweep_bench(args):
     """C4: one multi-instance sweep (every instance's lattice step in shared
     batched launches of uneven matrices, plus all impurity updates), recorded
     once in a hipGraph and replayed; seconds per sweep and the achieved rate of
-    the inversions (8 N_c^3 flops per point, summed over the instances)."""
+    the inversions (8 N_c^3 flops per point, summed over the instances).
+    With --tol > 0: every instance from Sigma = 0 until its delta falls below
+    tol (then it retires and the graph is re-recorded), at most --max-sweeps."""
     import torch
 
     from paper_0711_0999_amd import configs, fkdmft
 
     inst = configs.c4_instances(count=args.instances)
-    flops = sum(8.0 * (round((2 * d["t_max"] + 30) / d["dt"])) ** 3 * d["n_eps"] * d["n_ebar"]
-                for d in inst)
+    n_cs_of = [int(round((2 * d["t_max"] + 30) / d["dt"])) for d in inst]
+    per_iter = [8.0 * nc ** 3 * d["n_eps"] * d["n_ebar"] for nc, d in zip(n_cs_of, inst)]
+    flops = sum(per_iter)
+    if args.tol > 0:
+        with fkdmft.Batch(inst) as b:
+            if args.batch_autotune:
+                t0 = time.perf_counter()
+                tune = b.autotune(max_bytes=args.tune_bytes or 48 * 2.0 ** 30)
+                log(f"bench: batch autotune {time.perf_counter() - t0:.1f} s: {tune}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = b.iterate(args.max_sweeps, tol=args.tol, use_graph=True)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            tm = b.timings()
+        iters = [int(v) for v in r["iters"]]
+        done = [bool(d < args.tol) for d in r["deltas"]]
+        alg = sum(i * f for i, f in zip(iters, per_iter))
+        achieved = alg / sec / 1e12
+        print(json.dumps({
+            "metric": f"seconds to delta < {args.tol:g} for every instance of the C4 sweep",
+            "value": sec, "unit": "s", "n_gpus": 1, "steps": r["sweeps"], "warmup": 0,
+            "ms_per_step": sec * 1e3 / max(r["sweeps"], 1), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+            "config": {"workload": f"C4: {len(inst)} instances (rng 0), N_c in "
+                                   f"{sorted(set(n_cs_of))}, n x n points, n = 35..55, "
+                                   "from Sigma = 0, retirement, hipGraph replay",
+                       "parallelism": "1 GPU"},
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                         "traffic": None,
+                         "kernel": "whole sweeps (lattice inversions, 8 N_c^3 per point; "
+                                   "impurity updates and reductions in the time only)"},
+            "instances": [dict(U=d["U"], E=d["E"], dt=d["dt"], t_max=d["t_max"], n_c=nc,
+                               n=d["n_eps"], iters=i, converged=c, delta=float(dl))
+                          for d, nc, i, c, dl in zip(inst, n_cs_of, iters, done, r["deltas"])],
+            "converged": sum(done), "sweeps": r["sweeps"],
+            "graph": {"captures": tm["captures"], "capture_ms": tm["capture_ms"]},
+            "tuning": tm.get("tuning"),
+        }), flush=True)
+        return
     with fkdmft.Batch(inst) as b:
         t0 = time.perf_counter()
         b.iterate(max(args.warmup, 1), tol=0.0, use_graph=True)
@@ -112,13 +167,121 @@ def sweep_bench(args):
     }), flush=True)
 
 
+def converge_bench(args):
+    """The headline loops on the full C2 grid (55 x 55 points, N_c = 1800) for
+    each U: from Sigma = 0 to delta < 1e-8 in FP64 ("fp64") and with the
+    precision switch (complex64 steps, then FP64: "switch"), and ("warm", needs
+    --weights) from the network's judged proposal on the converged Sigma at
+    E - 0.25 in the switching loop, beside the same loop from that previous
+    field alone.  Fraction of the matrix-core peak: the time the run's lattice
+    steps would take at peak (8 N_c^3 per point: FP64 steps at the FP64 peak,
+    complex64 steps at the FP32 peak) over the measured time."""
+    import numpy as np
+    import torch
+
+    from paper_0711_0999_amd import configs, fkdmft
+
+    stream = torch.cuda.current_stream()
+    runs = []
+    tol = configs.C2_TOL
+    for U in args.Us:
+        w = configs.c2(U)
+        n = 1800
+        F = 8.0 * n ** 3 * w.n_eps * w.n_ebar
+
+        def frac_of(n64, n32, sec):
+            ideal = n64 * F / (PEAK_FP64_TFLOPS * 1e12) + n32 * F / (PEAK_FP32_TFLOPS * 1e12)
+            return ideal / sec
+
+        def make(E=w.E):
+            c = fkdmft.Context(stream=stream, **dict(w.kwargs(), E=E))
+            c.set_tuning(tile_rows=64, batch=args.batch or 757, lookahead=0)
+            c.set_refinement(0)
+            c.compute_gloc(fkdmft.FK_FP64)       # allocations outside the timing
+            c.compute_gloc(fkdmft.FK_MIXED)
+            c.set_sigma(np.zeros((c.n_c, c.n_c), np.complex128))
+            return c
+
+        def timed_loop(c, prec, judged_fallback=None):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if judged_fallback is None:
+                r = c.iterate(200, tol=tol, precision=prec)
+            else:
+                r = c.iterate_judged(judged_fallback, 200, tol=tol, accept=0.5,
+                                     precision=prec)
+            torch.cuda.synchronize()
+            return r, time.perf_counter() - t0
+
+        for form in args.forms:
+            if form in ("fp64", "switch"):
+                c = make()
+                prec = fkdmft.FK_FP64 if form == "fp64" else fkdmft.FK_MIXED
+                r, sec = timed_loop(c, prec)
+                n32 = c.low_iterations()
+                rec = dict(U=U, form=form, start="zero", iters=r["iters"], complex64_iters=n32,
+                           seconds=sec, sec_per_iter=sec / max(r["iters"], 1),
+                           converged=r["converged"], delta=r["delta"],
+                           frac_of_peak=frac_of(r["iters"] - n32, n32, sec))
+                c.close()
+            else:
+                from paper_0711_0999_amd import warmstart
+                ws = warmstart.WarmStart.load(args.weights)
+                cont = warmstart.EVAL_CONTOUR
+                c0 = make(E=w.E - warmstart.FIELD_STEP)
+                r0, sec0 = timed_loop(c0, fkdmft.FK_MIXED)
+                prev = torch.empty((c0.n_c, c0.n_c), dtype=torch.complex128, device="cuda")
+                c0.get_sigma(prev)
+                c0.close()
+                c = make()
+                c.set_sigma(prev)
+                rp, secp = timed_loop(c, fkdmft.FK_MIXED)
+                n32p = c.low_iterations()
+                c.close()
+                c = make()
+                prop_s = ws.propose(c, cont, prev, U, w.E)     # timed inside
+                r, sec = timed_loop(c, fkdmft.FK_MIXED, judged_fallback=prev)
+                sec += prop_s                  # the proposal counts in the start's time
+                n32 = c.low_iterations()
+                rec = dict(U=U, form="warm", start="network (judged), switching loop",
+                           iters=r["iters"], complex64_iters=n32, seconds=sec,
+                           propose_s=prop_s, outcome=r["outcome"],
+                           sec_per_iter=sec / max(r["iters"], 1),
+                           converged=r["converged"], delta=r["delta"],
+                           frac_of_peak=frac_of(r["iters"] - n32, n32, sec),
+                           previous_field=dict(iters=rp["iters"], complex64_iters=n32p,
+                                               seconds=secp, converged=rp["converged"]),
+                           previous_field_solve=dict(E=w.E - warmstart.FIELD_STEP,
+                                                     iters=r0["iters"], seconds=sec0))
+                c.close()
+            runs.append(rec)
+            log(f"bench: U={U} {form}: {rec['iters']} iterations in {rec['seconds']:.1f} s "
+                f"({rec['complex64_iters']} complex64), frac {rec['frac_of_peak']:.3f}")
+    print(json.dumps({
+        "metric": "sec/DMFT iteration at N_c=1800, FP64 vs mixed @1e-8; iters to converge",
+        "value": None, "unit": "s", "n_gpus": 1, "steps": 0, "warmup": 0,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128/c64", "data": "synthetic",
+        "config": {"workload": "C2 full grid: N_c=1800, 55x55 GH points, E=1, beta=10, "
+                               f"tol {tol:g}, U in {list(args.Us)}", "parallelism": "1 GPU"},
+        "runs": runs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--U", type=float, default=1.0)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "long"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c4", "long", "c2-converge"])
+    ap.add_argument("--Us", type=float, nargs="+", default=[0.5, 1.0, 1.5, 2.0])
+    ap.add_argument("--forms", nargs="+", default=["fp64", "switch"],
+                    choices=["fp64", "switch", "warm"])
+    ap.add_argument("--weights", default="")
+    ap.add_argument("--tol", type=float, default=0.0)
+    ap.add_argument("--max-sweeps", type=int, default=80)
+    ap.add_argument("--batch-autotune", action="store_true")
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--converge", action="store_true")
@@ -144,6 +307,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "c4":
         sweep_bench(args)
+        return
+    if args.workload == "c2-converge":
+        converge_bench(args)
         return
     stream = torch.cuda.current_stream()
     w = {"c2": lambda: configs.c2(args.U), "c1": lambda: configs.C1,
@@ -199,17 +365,20 @@ def main():
     # textbook 2 N^3 of a real inversion, four real products per complex one)
     flops_iter = 8.0 * n ** 3 * npts
     inversion_tflops = flops_iter * args.steps / (step_ms * 1e-3) / 1e12
-    # dominant kernel: the trailing update of each outer block, timed per launch;
-    # its algorithmic flops count 8 real flops per complex multiply-add, while
-    # the kernel forms each complex product from three real ones, so its matrix
-    # cores execute 3/4 of that count ("mfma_frac")
-    achieved = kc["flop"] / (kc["ms"] * 1e-3) / 1e12
+    # dominant kernel: the trailing update of each outer block (pair), timed
+    # per launch.  Primary rate: the flops its matrix cores execute (three real
+    # products per complex one, 6 real flops per complex multiply-add), which
+    # the peak bounds; beside it the algorithmic rate (8 per complex
+    # multiply-add), which exceeds the peak once the kernel passes 3/4 of it
+    alg_tflops = kc["flop"] / (kc["ms"] * 1e-3) / 1e12
+    achieved = EXECUTED_PER_ALGORITHMIC * alg_tflops
     peak = PEAK_FP32_TFLOPS if args.mixed else PEAK_FP64_TFLOPS
     tuned = ctx.get_tuning()
     kname = (f"fk::k_update<{'float' if args.mixed else 'double'}, "
              f"{2 if tuned['tile_rows'] == 64 else 4}>")
     traffic = (PROFILED_TRAFFIC["bytes_per_launch"]
-               if (kname == PROFILED_TRAFFIC["kernel"] and w.name.startswith("C2")
+               if (PROFILED_TRAFFIC and kname == PROFILED_TRAFFIC["kernel"]
+                   and w.name.startswith("C2")
                    and tuned["batch"] == PROFILED_TRAFFIC["batch"]) else None)
     out = {
         "metric": ("sec/DMFT iteration at N_c=1800, FP64 vs mixed @1e-8; iters to converge"
@@ -232,11 +401,15 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "kernel": kname,
+                     "flops_counted": "executed matrix-core flops (3 real products "
+                                      "per complex product)",
                      "launches": kc["launches"],
-                     "flops_per_launch": kc["flop"] / max(kc["launches"], 1),
+                     "executed_flops_per_launch":
+                         EXECUTED_PER_ALGORITHMIC * kc["flop"] / max(kc["launches"], 1),
+                     "algorithmic_flops_per_launch": kc["flop"] / max(kc["launches"], 1),
                      "avg_launch_ms": kc["ms"] / max(kc["launches"], 1),
-                     "mfma_flops_per_launch": 0.75 * kc["flop"] / max(kc["launches"], 1),
-                     "mfma_frac": 0.75 * achieved / peak,
+                     "algorithmic_tflops": alg_tflops,
+                     "algorithmic_frac": alg_tflops / peak,
                      "whole_inversion_tflops": inversion_tflops,
                      "whole_inversion_frac": inversion_tflops / peak},
         "phases_ms_last_step": {k: round(v, 3) for k, v in tm_last.items()},
@@ -282,7 +455,10 @@ def main():
     if not args.converge:
         conv_kw.update(n_eps=15, n_ebar=15)
     if not args.no_converge:
-        conv = {"points": conv_kw["n_eps"] * conv_kw["n_ebar"], "tol": configs.C2_TOL}
+        conv = {"grid": f"{conv_kw['n_eps']}x{conv_kw['n_ebar']} points on the C2 contour"
+                        + ("" if args.converge else
+                           " (reduced grid; full-grid runs: --workload c2-converge)"),
+                "points": conv_kw["n_eps"] * conv_kw["n_ebar"], "tol": configs.C2_TOL}
         for name, p2 in (("fp64", fkdmft.FK_FP64), ("mixed_switch", fkdmft.FK_MIXED)):
             ctx2 = fkdmft.Context(stream=stream, **conv_kw)
             if args.converge:

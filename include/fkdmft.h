@@ -211,7 +211,8 @@ fk_status fk_impurity_update(fk_ctx* ctx, double* max_dsigma_out);
  * case exactly max_iter iterations run and FK_OK is returned).
  * With FK_MIXED the loop runs complex64 (+ refinement) steps until delta <
  * switch_tol (fk_set_switch, default 3e-5, above the complex64 noise floor of
- * G_loc) or stops contracting (delta(n) > 0.95 delta(n-1)), FK_FP64 afterwards.
+ * G_loc) or stops contracting close to that floor (delta(n) > 0.95 delta(n-1)
+ * with delta(n) < 100 switch_tol), FK_FP64 afterwards.
  * delta_history (nullable, max_iter doubles) receives delta(n). */
 fk_status fk_iterate(fk_ctx* ctx, int max_iter, double tol, fk_precision prec,
                      int* iters_out, double* delta_out, double* delta_history);
@@ -300,6 +301,17 @@ fk_status fk_batch_iterate(fk_batch* b, int max_sweeps, double tol,
                            double* deltas);
 /* Tile height, look-ahead and chunk_bytes of t apply to every sweep. */
 fk_status fk_batch_set_tuning(fk_batch* b, const fk_tuning* t);
+/* Autotuner of the sweep's schedule per contour size: for every distinct N_c
+ * among the instances, fk_autotune on the first instance of that size (its
+ * own point matrices and current Sigma, candidate tile heights x matrices per
+ * chunk within max_bytes); the sweep's plan then orders the instances by size,
+ * cuts chunks within one size class of at most that class's tuned number of
+ * matrices and runs them with its tile height.  Returns the number of classes
+ * and (up to max_out, nullable) their sizes and schedules.  The chunk storage
+ * is released first (the trials need the memory); fk_batch_set_tuning returns
+ * to one schedule for all. */
+fk_status fk_batch_autotune(fk_batch* b, double max_bytes, int max_out,
+                            int* n_classes, int* class_nc, fk_tuning* class_tuning);
 /* out4: last sweep ms, total sweep ms, graph recordings, last recording ms. */
 fk_status fk_batch_timings(const fk_batch* b, double* out4);
 

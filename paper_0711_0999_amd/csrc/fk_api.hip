@@ -940,7 +940,7 @@ namespace {
 // max |G_loc - G_loc of the previous iteration| from the second iteration on,
 // impurity update (dsig: max |Sigma_new - Sigma|, nullable).  In a mixed run the
 // low-precision phase ends below switch_tol, or as soon as delta stops
-// contracting (it has reached the complex64 noise floor).
+// contracting below 100 switch_tol (it has reached the complex64 noise floor).
 fk_status iteration(fk_ctx* c, int it, bool* low, double* delta, double* prev_delta,
                     double* hist, double* dsig) {
   if (*low) c->low_iters++;
@@ -959,7 +959,11 @@ fk_status iteration(fk_ctx* c, int it, bool* low, double* delta, double* prev_de
                            hipMemcpyDeviceToDevice, c->st));
   s = impurity(c, dsig);
   if (s != FK_OK) return s;
-  if (*low && (*delta < c->switch_tol || (it > 2 && *delta > 0.95 * *prev_delta)))
+  // leave the complex64 phase below switch_tol, or when delta stops
+  // contracting close to the complex64 noise floor (a stall far above it, as in
+  // the first iterations of a slowly contracting loop, is not a precision limit)
+  if (*low && (*delta < c->switch_tol ||
+               (it > 2 && *delta < 100.0 * c->switch_tol && *delta > 0.95 * *prev_delta)))
     *low = false;
   *prev_delta = *delta;
   return FK_OK;

@@ -106,6 +106,10 @@ struct fk_batch {
   double capture_ms = 0.0, last_sweep_ms = 0.0, total_ms = 0.0;
   int max_nc = 0;
   int variant = 0;
+  // per N_c class schedule from fk_batch_autotune (empty: one schedule for
+  // all, chunk_bytes and variant above)
+  std::vector<int> class_nc;
+  std::vector<fk_tuning> class_tuning;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
 };
@@ -155,28 +159,62 @@ void borrow(fk::Batch<double>& cb, c64* x, size_t xc, c64* bb, size_t bc,
 }
 
 // Chunk plan for the active instances: point matrices ordered by instance,
-// cut into chunks that fit chunk_bytes; impurity slots after them.
+// cut into chunks that fit chunk_bytes; impurity slots after them.  With a
+// per-class schedule (fk_batch_autotune) the instances are ordered by contour
+// size, a chunk holds one size class only, at most that class's tuned number
+// of matrices, and runs that class's tile shape.
+int class_of(const fk_batch* b, int n_c) {
+  for (size_t q = 0; q < b->class_nc.size(); ++q)
+    if (b->class_nc[q] == n_c) return (int)q;
+  return -1;
+}
+
 fk_status build_plan(fk_batch* b) {
   drop_graph(b);
   for (Chunk& c : b->chunks) batch_free(c.b);
   b->chunks.clear();
   struct Job { int inst, k; };
+  std::vector<int> order = b->active;
+  const bool per_class = !b->class_nc.empty();
+  if (per_class)
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return b->inst[x]->ci.n_c < b->inst[y]->ci.n_c;
+    });
   std::vector<std::vector<Job>> groups(1);
+  std::vector<int> group_variant(1, b->variant);
   double used = 0.0;
-  for (int id : b->active) {
+  int used_mats = 0, cur_class = -2;
+  for (int id : order) {
     const fk_ctx* c = b->inst[id];
     const double n = c->ci.n_c;
     const double per = 16.0 * (n * n + kBRows * n) + 8.0 * n;
+    const int cls = per_class ? class_of(b, c->ci.n_c) : -1;
+    double cap_bytes = b->chunk_bytes;
+    int cap_mats = 1 << 30, variant = b->variant;
+    if (cls >= 0) {
+      cap_bytes = std::numeric_limits<double>::max();   // the tuned count was sized in bytes
+      cap_mats = std::max(1, b->class_tuning[cls].batch);
+      variant = b->class_tuning[cls].tile_rows == 128 ? 1 : 0;
+    }
     for (int k = 0; k < c->npts; ++k) {
-      if (used + per > b->chunk_bytes && !groups.back().empty()) {
+      const bool full = used + per > cap_bytes || used_mats >= cap_mats;
+      if (!groups.back().empty() && (full || (per_class && cls != cur_class))) {
         groups.emplace_back();
+        group_variant.push_back(variant);
         used = 0.0;
+        used_mats = 0;
       }
+      if (groups.back().empty()) group_variant.back() = variant;
+      cur_class = cls;
       groups.back().push_back(Job{id, k});
       used += per;
+      ++used_mats;
     }
   }
-  if (groups.back().empty()) groups.pop_back();
+  if (groups.back().empty()) {
+    groups.pop_back();
+    group_variant.pop_back();
+  }
   // storage needs
   size_t xmax = 0, bmax = 0, imax = 0;
   int status = 0;
@@ -207,7 +245,7 @@ fk_status build_plan(fk_batch* b) {
   for (size_t g = 0; g < groups.size(); ++g) {
     Chunk& ch = b->chunks[g];
     borrow(ch.b, b->x, b->x_cap, b->bbuf, b->b_cap, b->piv, b->rowcol, b->i_cap);
-    ch.b.variant = b->variant;
+    ch.b.variant = group_variant[g];
     BCHK(b, batch_setup_uneven(ch.b, sizes[g], sidx[g]));
     size_t xo = 0, io = 0;
     for (const Job& j : groups[g]) {
@@ -573,6 +611,51 @@ extern "C" fk_status fk_batch_set_tuning(fk_batch* b, const fk_tuning* t) {
   b->variant = t->tile_rows == 128 ? 1 : 0;
   b->aux.lookahead = t->lookahead != 0;
   if (t->chunk_bytes > 0) b->chunk_bytes = t->chunk_bytes;
+  b->class_nc.clear();          // one schedule for every size class
+  b->class_tuning.clear();
   b->dirty = true;
+  return FK_OK;
+}
+
+extern "C" fk_status fk_batch_autotune(fk_batch* b, double max_bytes, int max_out,
+                                       int* n_classes, int* class_nc,
+                                       fk_tuning* class_tuning) {
+  if (!b || !(max_bytes > 0) || max_out < 0) return FK_EINVAL;
+  // one representative instance per contour size (the first of each)
+  std::vector<int> ncs, rep_inst;
+  for (int i = 0; i < (int)b->inst.size(); ++i) {
+    const int nc = b->inst[i]->ci.n_c;
+    if (std::find(ncs.begin(), ncs.end(), nc) == ncs.end()) {
+      ncs.push_back(nc);
+      rep_inst.push_back(i);
+    }
+  }
+  std::vector<fk_tuning> tun(ncs.size());
+  // the shared chunk storage is released first so the trials have the memory
+  drop_graph(b);
+  for (Chunk& c : b->chunks) batch_free(c.b);
+  b->chunks.clear();
+  void* shared[] = {b->x, b->bbuf, b->piv, b->rowcol};
+  for (void* p : shared)
+    if (p) (void)hipFree(p);
+  b->x = nullptr;
+  b->bbuf = nullptr;
+  b->piv = b->rowcol = nullptr;
+  b->x_cap = b->b_cap = b->i_cap = b->i2_cap = 0;
+  for (size_t q = 0; q < ncs.size(); ++q) {
+    fk_ctx* c = b->inst[rep_inst[q]];
+    const fk_status s = fk_autotune(c, max_bytes, 0, &tun[q]);
+    if (s != FK_OK)
+      return berr(b, s, "autotune of N_c = %d (instance %d): %s", ncs[q], rep_inst[q],
+                  fk_last_error(c));
+  }
+  b->class_nc = ncs;
+  b->class_tuning = tun;
+  b->dirty = true;
+  if (n_classes) *n_classes = (int)ncs.size();
+  for (int q = 0; q < (int)ncs.size() && q < max_out; ++q) {
+    if (class_nc) class_nc[q] = ncs[q];
+    if (class_tuning) class_tuning[q] = tun[q];
+  }
   return FK_OK;
 }

@@ -204,7 +204,8 @@ def _error_regions(ctx, cont, prev, start, fixed):
 
 
 def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
-                   mixed=True, log=None, also_accept=()):
+                   mixed=True, log=None, also_accept=(),
+                   starts=("zero", "equilibrium", "previous", "network", "network_mixed")):
     """Iterations to tol at (U, E) from Sigma = 0, from the equilibrium Sigma
     (E = 0, same contour), from the converged Sigma of E - dE (previous field)
     and from the network's proposal on it (judged, with the previous field as
@@ -222,15 +223,16 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
         out["n_c"] = c.n_c
     # the paper's usual guess: the equilibrium self-energy (E = 0 on the same
     # contour), independent of the field
-    with fkdmft.Context(**cont, U=u, E=0.0, n_eps=n_eps, n_ebar=n_ebar) as c:
-        r = c.iterate(max_iter, tol=tol)
-        equil = torch.empty((c.n_c, c.n_c), dtype=torch.complex128, device="cuda")
-        c.get_sigma(equil)
-        out["equilibrium_solve_iters"] = r["iters"]
+    if "equilibrium" in starts:
+        with fkdmft.Context(**cont, U=u, E=0.0, n_eps=n_eps, n_ebar=n_ebar) as c:
+            r = c.iterate(max_iter, tol=tol)
+            equil = torch.empty((c.n_c, c.n_c), dtype=torch.complex128, device="cuda")
+            c.get_sigma(equil)
+            out["equilibrium_solve_iters"] = r["iters"]
     glocs = {}
-    starts = (["zero", "equilibrium", "previous", "network"]
-              + (["network_mixed"] if mixed else [])
+    starts = ([s for s in starts if s != "network_mixed" or mixed]
               + [f"network_accept{a:g}" for a in also_accept])
+    assert starts[0] == "zero", "the Sigma = 0 run defines the fixed point"
     fixed = None
     for start in starts:
         with fkdmft.Context(**cont, U=u, E=e, n_eps=n_eps, n_ebar=n_ebar) as c:
@@ -271,10 +273,10 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
     out["gloc_spread"] = max(float(np.max(np.abs(g - ref))) for g in glocs.values())
     if log:
         log(f"U={u:.3f} E={e:.3f} N_c={out['n_c']}: iterations zero {out['zero_iters']}, "
-            f"equilibrium {out['equilibrium_iters']}, "
-            f"previous {out['previous_iters']}, network {out['network_iters']} "
-            f"(outcome {out['network_outcome']})"
-            + (f", network+mixed {out['network_mixed_iters']}" if mixed else "")
+            f"equilibrium {out.get('equilibrium_iters')}, "
+            f"previous {out.get('previous_iters')}, network {out.get('network_iters')} "
+            f"(outcome {out.get('network_outcome')})"
+            + (f", network+mixed {out.get('network_mixed_iters')}" if mixed else "")
             + "".join(f", accept {a:g}: {out[f'network_accept{a:g}_iters']}"
                       for a in also_accept)
             + f"; start error max/rms previous {out.get('start_err_previous')}, "
@@ -293,6 +295,16 @@ EVAL_CONTOUR = dict(t_min=-10.0, t_max=30.0, dt=0.05, dtau=0.05, beta=10.0)
 FIELDS = tuple(0.5 + FIELD_STEP * k for k in range(15))        # 0.5 .. 4.0
 
 
+def unseen_cases(count, seed=2):
+    """Evaluation pairs (U, E): U ~ U[0.25, 2.5], E ~ U[0.75, 4] drawn with
+    numpy's default_rng(seed), so they are off the training runs' (U, E) (the
+    training U are other draws; E lies between the training fields with
+    probability one).  E >= 0.75 leaves room for the previous field E - 0.25."""
+    rng = np.random.default_rng(seed)
+    return [(float(rng.uniform(0.25, 2.5)), float(rng.uniform(0.75, 4.0)))
+            for _ in range(count)]
+
+
 def _main(argv=None):
     import argparse
     import json
@@ -301,9 +313,12 @@ def _main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     tr = sub.add_parser("train", help="generate field sweeps, train, save")
     tr.add_argument("--out", required=True)
-    tr.add_argument("--n-u", type=int, nargs=2, default=[60, 16],
-                    help="U values per training contour")
-    tr.add_argument("--u-range", type=float, nargs=2, default=[0.25, 1.75])
+    tr.add_argument("--n-u", type=int, nargs=2, default=[100, 34],
+                    help="U values per training contour (dt = 0.2, dt = 0.1)")
+    tr.add_argument("--u-range", type=float, nargs=2, default=[0.25, 1.9],
+                    help="U range on the dt = 0.2 contour (where its loop converges)")
+    tr.add_argument("--u-range-fine", type=float, nargs=2, default=[0.25, 2.5],
+                    help="U range on the dt = 0.1 contour")
     tr.add_argument("--gh", type=int, default=10)
     tr.add_argument("--tol", type=float, default=1e-6)
     tr.add_argument("--rows", type=int, default=4096)
@@ -314,8 +329,12 @@ def _main(argv=None):
     ev = sub.add_parser("evaluate", help="compare starts on unseen (U, E)")
     ev.add_argument("--weights", required=True)
     ev.add_argument("--out", required=True)
-    ev.add_argument("--cases", type=float, nargs="+",
-                    default=[0.6, 1.3, 1.1, 2.05, 1.45, 3.3])
+    ev.add_argument("--cases", type=float, nargs="+", default=None,
+                    help="U E pairs (default: --n-cases unseen pairs)")
+    ev.add_argument("--n-cases", type=int, default=32)
+    ev.add_argument("--first-case", type=int, default=0)
+    ev.add_argument("--starts", nargs="+",
+                    default=["zero", "equilibrium", "previous", "network", "network_mixed"])
     ev.add_argument("--gh", type=int, default=15)
     ev.add_argument("--tol", type=float, default=1e-8)
     ev.add_argument("--also-accept", type=float, nargs="*", default=[])
@@ -329,8 +348,8 @@ def _main(argv=None):
         rng = np.random.default_rng(a.seed)
         xs, ts, stats = [], [], []
         t0 = time.perf_counter()
-        for cont, n_u in zip(TRAIN_CONTOURS, a.n_u):
-            us = np.sort(rng.uniform(a.u_range[0], a.u_range[1], n_u))
+        for cont, n_u, ur in zip(TRAIN_CONTOURS, a.n_u, (a.u_range, a.u_range_fine)):
+            us = np.sort(rng.uniform(ur[0], ur[1], n_u))
             log(f"contour dt={cont['dt']}: {n_u} values of U")
             x, t, st = field_sweep_data(cont, list(us), list(FIELDS), a.gh, a.gh, a.tol,
                                         a.rows, seed=int(rng.integers(1 << 31)),
@@ -357,10 +376,15 @@ def _main(argv=None):
         log(f"saved {a.out}: {runs} runs, {pairs} pairs")
     else:
         ws = WarmStart.load(a.weights)
+        if a.cases:
+            cases = list(zip(a.cases[0::2], a.cases[1::2]))
+        else:
+            cases = unseen_cases(a.n_cases)[a.first_case:]
         res = []
-        for u, e in zip(a.cases[0::2], a.cases[1::2]):
+        for u, e in cases:
             res.append(compare_starts(ws, EVAL_CONTOUR, u, e, a.gh, a.gh, a.tol, log=log,
-                                      also_accept=tuple(a.also_accept)))
+                                      also_accept=tuple(a.also_accept),
+                                      starts=tuple(a.starts)))
             with open(a.out, "w") as f:
                 json.dump(res, f, indent=1)
 

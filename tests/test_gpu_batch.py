@@ -174,3 +174,20 @@ def test_batch_zero_pivot_names_instance_and_point(lib):
             b.iterate(1, tol=0.0, use_graph=False)
         assert err.value.status == lib.FK_ESINGULAR
         assert "instance 1: zero pivot at column 5 of matrix 4" in str(err.value), str(err.value)
+
+
+def test_batch_autotune_per_size_class(lib):
+    """fk_batch_autotune picks a schedule per contour size (tile height,
+    matrices per chunk) on each class's own matrices; sweeps with the per-class
+    plan (one size class per chunk) give the results of the default plan."""
+    print("case: batch autotune per N_c class", flush=True)
+    with lib.Batch(INSTANCES) as b, lib.Batch(INSTANCES) as ref:
+        cls = b.autotune(max_bytes=64 * 2 ** 20)
+        assert sorted(c["n_c"] for c in cls) == [73, 150, 200]
+        assert all(c["tile_rows"] in (64, 128) and c["batch"] >= 1 and c["trials"] >= 2
+                   for c in cls)
+        b.iterate(2, tol=0.0, use_graph=True)
+        ref.iterate(2, tol=0.0, use_graph=True)
+        for i in range(3):
+            assert relerr(b.instance(i).get_gloc(), ref.instance(i).get_gloc()) < 1e-13
+            assert relerr(b.instance(i).get_sigma(), ref.instance(i).get_sigma()) < 1e-12
