@@ -104,16 +104,36 @@ def sweep_bench(args):
     flops = sum(per_iter)
     if args.tol > 0:
         with fkdmft.Batch(inst) as b:
+            tune = None
             if args.batch_autotune:
                 t0 = time.perf_counter()
-                tune = b.autotune(max_bytes=args.tune_bytes or 48 * 2.0 ** 30)
-                log(f"bench: batch autotune {time.perf_counter() - t0:.1f} s: {tune}")
+                for nc in sorted(set(n_cs_of)):      # one size class per call
+                    tune = b.autotune(max_bytes=args.tune_bytes or 48 * 2.0 ** 30,
+                                      only_nc=nc)
+                    log(f"bench: autotuned N_c = {nc} "
+                        f"({time.perf_counter() - t0:.1f} s): "
+                        f"{[t for t in tune if t['n_c'] == nc][0]}")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = b.iterate(args.max_sweeps, tol=args.tol, use_graph=True)
+            # one sweep per call (the batch keeps its state, retires converged
+            # instances and re-records the graph when the active set changes),
+            # so progress shows and a time budget can end the run early
+            sweeps = 0
+            while sweeps < args.max_sweeps:
+                r = b.iterate(1, tol=args.tol, use_graph=True)
+                if r["sweeps"] == 0:
+                    break
+                sweeps += 1
+                done = [bool(d < args.tol) for d in r["deltas"]]
+                el = time.perf_counter() - t0
+                log(f"bench: sweep {sweeps}: {sum(done)}/{len(done)} converged, "
+                    f"{el:.0f} s, last {b.timings()['last_sweep_ms']:.0f} ms")
+                if all(done) or el > args.time_budget:
+                    break
             torch.cuda.synchronize()
             sec = time.perf_counter() - t0
             tm = b.timings()
+            r["sweeps"] = sweeps
         iters = [int(v) for v in r["iters"]]
         done = [bool(d < args.tol) for d in r["deltas"]]
         alg = sum(i * f for i, f in zip(iters, per_iter))
@@ -136,8 +156,10 @@ def sweep_bench(args):
                                n=d["n_eps"], iters=i, converged=c, delta=float(dl))
                           for d, nc, i, c, dl in zip(inst, n_cs_of, iters, done, r["deltas"])],
             "converged": sum(done), "sweeps": r["sweeps"],
+            "stopped_by": ("all converged" if all(done) else
+                           "time budget" if sec > args.time_budget else "sweep cap"),
             "graph": {"captures": tm["captures"], "capture_ms": tm["capture_ms"]},
-            "tuning": tm.get("tuning"),
+            "tuning": tune if args.batch_autotune else None,
         }), flush=True)
         return
     with fkdmft.Batch(inst) as b:
@@ -230,6 +252,8 @@ def converge_bench(args):
                 cont = warmstart.EVAL_CONTOUR
                 c0 = make(E=w.E - warmstart.FIELD_STEP)
                 r0, sec0 = timed_loop(c0, fkdmft.FK_MIXED)
+                log(f"bench: U={U} previous field E={w.E - warmstart.FIELD_STEP}: "
+                    f"{r0['iters']} iterations in {sec0:.1f} s")
                 prev = torch.empty((c0.n_c, c0.n_c), dtype=torch.complex128, device="cuda")
                 c0.get_sigma(prev)
                 c0.close()
@@ -238,6 +262,8 @@ def converge_bench(args):
                 rp, secp = timed_loop(c, fkdmft.FK_MIXED)
                 n32p = c.low_iterations()
                 c.close()
+                log(f"bench: U={U} from the previous field: {rp['iters']} iterations "
+                    f"in {secp:.1f} s")
                 c = make()
                 prop_s = ws.propose(c, cont, prev, U, w.E)     # timed inside
                 r, sec = timed_loop(c, fkdmft.FK_MIXED, judged_fallback=prev)
@@ -281,6 +307,8 @@ def main():
     ap.add_argument("--weights", default="")
     ap.add_argument("--tol", type=float, default=0.0)
     ap.add_argument("--max-sweeps", type=int, default=80)
+    ap.add_argument("--time-budget", type=float, default=900.0,
+                    help="c4 with --tol: stop starting sweeps after this many seconds")
     ap.add_argument("--batch-autotune", action="store_true")
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--mixed", action="store_true")

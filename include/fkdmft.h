@@ -302,15 +302,17 @@ fk_status fk_batch_iterate(fk_batch* b, int max_sweeps, double tol,
 /* Tile height, look-ahead and chunk_bytes of t apply to every sweep. */
 fk_status fk_batch_set_tuning(fk_batch* b, const fk_tuning* t);
 /* Autotuner of the sweep's schedule per contour size: for every distinct N_c
- * among the instances, fk_autotune on the first instance of that size (its
- * own point matrices and current Sigma, candidate tile heights x matrices per
- * chunk within max_bytes); the sweep's plan then orders the instances by size,
- * cuts chunks within one size class of at most that class's tuned number of
- * matrices and runs them with its tile height.  Returns the number of classes
- * and (up to max_out, nullable) their sizes and schedules.  The chunk storage
- * is released first (the trials need the memory); fk_batch_set_tuning returns
- * to one schedule for all. */
-fk_status fk_batch_autotune(fk_batch* b, double max_bytes, int max_out,
+ * among the instances (only_nc = 0), or for the instances of size only_nc
+ * alone (merged into the table), fk_autotune on the first instance of that
+ * size (its own point matrices and current Sigma, candidate tile heights x
+ * matrices per chunk within max_bytes); the sweep's plan then orders the
+ * instances by size, cuts chunks within one size class of at most that
+ * class's tuned number of matrices and runs them with its tile height.
+ * Returns the number of classes in the table and (up to max_out, nullable)
+ * their sizes and schedules.  The chunk storage is released first (the trials
+ * need the memory); fk_batch_set_tuning returns to one schedule for all.
+ * FK_EINVAL when no instance has size only_nc. */
+fk_status fk_batch_autotune(fk_batch* b, double max_bytes, int only_nc, int max_out,
                             int* n_classes, int* class_nc, fk_tuning* class_tuning);
 /* out4: last sweep ms, total sweep ms, graph recordings, last recording ms. */
 fk_status fk_batch_timings(const fk_batch* b, double* out4);

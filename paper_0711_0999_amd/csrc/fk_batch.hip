@@ -617,19 +617,22 @@ extern "C" fk_status fk_batch_set_tuning(fk_batch* b, const fk_tuning* t) {
   return FK_OK;
 }
 
-extern "C" fk_status fk_batch_autotune(fk_batch* b, double max_bytes, int max_out,
-                                       int* n_classes, int* class_nc,
+extern "C" fk_status fk_batch_autotune(fk_batch* b, double max_bytes, int only_nc,
+                                       int max_out, int* n_classes, int* class_nc,
                                        fk_tuning* class_tuning) {
-  if (!b || !(max_bytes > 0) || max_out < 0) return FK_EINVAL;
+  if (!b || !(max_bytes > 0) || max_out < 0 || only_nc < 0) return FK_EINVAL;
   // one representative instance per contour size (the first of each)
   std::vector<int> ncs, rep_inst;
   for (int i = 0; i < (int)b->inst.size(); ++i) {
     const int nc = b->inst[i]->ci.n_c;
+    if (only_nc > 0 && nc != only_nc) continue;
     if (std::find(ncs.begin(), ncs.end(), nc) == ncs.end()) {
       ncs.push_back(nc);
       rep_inst.push_back(i);
     }
   }
+  if (ncs.empty())
+    return berr(b, FK_EINVAL, "no instance with N_c = %d", only_nc);
   std::vector<fk_tuning> tun(ncs.size());
   // the shared chunk storage is released first so the trials have the memory
   drop_graph(b);
@@ -649,13 +652,25 @@ extern "C" fk_status fk_batch_autotune(fk_batch* b, double max_bytes, int max_ou
       return berr(b, s, "autotune of N_c = %d (instance %d): %s", ncs[q], rep_inst[q],
                   fk_last_error(c));
   }
-  b->class_nc = ncs;
-  b->class_tuning = tun;
+  // merge into the per-class table (a single class replaces its own entry)
+  if (only_nc == 0) {
+    b->class_nc.clear();
+    b->class_tuning.clear();
+  }
+  for (size_t q = 0; q < ncs.size(); ++q) {
+    const int at = class_of(b, ncs[q]);
+    if (at >= 0) {
+      b->class_tuning[at] = tun[q];
+    } else {
+      b->class_nc.push_back(ncs[q]);
+      b->class_tuning.push_back(tun[q]);
+    }
+  }
   b->dirty = true;
-  if (n_classes) *n_classes = (int)ncs.size();
-  for (int q = 0; q < (int)ncs.size() && q < max_out; ++q) {
-    if (class_nc) class_nc[q] = ncs[q];
-    if (class_tuning) class_tuning[q] = tun[q];
+  if (n_classes) *n_classes = (int)b->class_nc.size();
+  for (int q = 0; q < (int)b->class_nc.size() && q < max_out; ++q) {
+    if (class_nc) class_nc[q] = b->class_nc[q];
+    if (class_tuning) class_tuning[q] = b->class_tuning[q];
   }
   return FK_OK;
 }

@@ -694,12 +694,14 @@ __global__ __launch_bounds__(512, 1) void k_fix(
 // WR x 2 blocks of 32 x 32 (WR = 2: 64 x 64 tiles, two workgroups per CU;
 // WR = 4: 128 x 64 tiles sharing each B chunk, one workgroup per CU).  K in
 // chunks of kKC, double-buffered through LDS with the next chunk's global
-// loads in flight during the current chunk's MFMAs.  Each complex product
-// takes three real ones (Gauss): P1 = Re a Re b, P2 = Im a Im b and
-// P3 = (Re a + Im a)(Re b + Im b) accumulate separately, and the epilogue
-// forms Re = P1 - P2, Im = P3 - P1 - P2: a quarter fewer MFMAs than the
-// four-product form, with a normwise (not componentwise) error bound of the
-// same order.
+// loads in flight during the current chunk's MFMAs; within a chunk the next
+// k-step's operands are read from LDS before the current k-step's MFMAs.
+// Interior tiles (whole rows, columns and K chunks) skip every clamp and
+// mask.  Each complex product takes three real ones (Gauss): P1 = Re a Re b,
+// P2 = Im a Im b and P3 = (Re a + Im a)(Re b + Im b) accumulate separately,
+// and the epilogue forms Re = P1 - P2, Im = P3 - P1 - P2: a quarter fewer
+// MFMAs than the four-product form, with a normwise (not componentwise) error
+// bound of the same order.  The C tile is read in the epilogue.
 template <typename T, int WR>
 __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
     cplx<T>* __restrict__ xbuf, const cplx<T>* __restrict__ bbuf,
@@ -712,6 +714,7 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
   __shared__ cplx<T> Bsh[2][kKC * BP];
   constexpr int kLA = TR * kKC / NT;      // chunk loads per thread
   constexpr int kLB = kKC * kTile / NT;
+  static_assert(NT % kKC == 0 && NT % kTile == 0, "load map");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -721,6 +724,11 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
   const int per = gridDim.x >> 3;
   const int chunk = (nitems + 7) >> 3;
   const int lo = xcd * chunk, hi = min(nitems, lo + chunk);
+  // this thread's chunk loads: A rows ai0 + t (NT / kKC) at column ak of the
+  // chunk, B rows bk0 + t (NT / kTile) at column bc of the tile
+  const int ak = tid % kKC, ai0 = tid / kKC;
+  const int bc = tid % kTile, bk0 = tid / kTile;
+  constexpr int AST = NT / kKC, BST = NT / kTile;
 
   for (int it = lo + slot; it < hi; it += per) {
     const TileItem ti = items[it];
@@ -733,29 +741,49 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
     cplx<T>* xm = xbuf + d.xoff;
     const cplx<T>* bm = bbuf + d.boff + (size_t)ti.b0 * ld;
     const int* rowcol = rowcolbuf + d.ioff;
+    const bool full = r0 + TR <= n && c0 + kTile <= n && (wO % kKC) == 0;
+    const cplx<T>* arow[kLA];
+#pragma unroll
+    for (int t = 0; t < kLA; ++t)
+      arow[t] = xm + (size_t)min(r0 + ai0 + AST * t, n - 1) * ld + J0;
+    const cplx<T>* bcol = bm + min(c0 + bc, n - 1);
+    cplx<T> pa[kLA], pb[kLB];
+    auto gload = [&](int kb) {
+      if (full) {
+#pragma unroll
+        for (int t = 0; t < kLA; ++t) pa[t] = arow[t][kb + ak];
+#pragma unroll
+        for (int t = 0; t < kLB; ++t) pb[t] = bcol[(size_t)(kb + bk0 + BST * t) * ld];
+      } else {
+#pragma unroll
+        for (int t = 0; t < kLA; ++t) pa[t] = arow[t][min(kb + ak, wO - 1)];
+#pragma unroll
+        for (int t = 0; t < kLB; ++t)
+          pb[t] = bcol[(size_t)min(kb + bk0 + BST * t, wO - 1) * ld];
+      }
+    };
+    auto lstore = [&](int kb, int buf) {
+      if (!full) {
+#pragma unroll
+        for (int t = 0; t < kLA; ++t)
+          if (!(r0 + ai0 + AST * t < n && kb + ak < wO)) pa[t].re = pa[t].im = T(0);
+#pragma unroll
+        for (int t = 0; t < kLB; ++t)
+          if (!(kb + bk0 + BST * t < wO && c0 + bc < n)) pb[t].re = pb[t].im = T(0);
+      }
+#pragma unroll
+      for (int t = 0; t < kLA; ++t) As[buf][(ai0 + AST * t) * AP + ak] = pa[t];
+#pragma unroll
+      for (int t = 0; t < kLB; ++t) Bsh[buf][(bk0 + BST * t) * BP + bc] = pb[t];
+    };
 
-    // pivot-row mask (the C tile itself is read during the last K chunk and
-    // added in the epilogue, so the MFMAs start as soon as chunk 0 is in LDS)
+    // pivot-row mask of the rows this lane writes
     int rcv[2][4];
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         rcv[ii][v] = rowcol[min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1)];
-    // chunk 0
-    cplx<T> pa[kLA], pb[kLB];
-#pragma unroll
-    for (int t = 0; t < kLA; ++t) {
-      const int e = tid + t * NT;
-      const int i = e / kKC, k = e % kKC;
-      pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(k, wO - 1)];
-    }
-#pragma unroll
-    for (int t = 0; t < kLB; ++t) {
-      const int e = tid + t * NT;
-      const int k = e / kTile, c = e % kTile;
-      pb[t] = bm[(size_t)min(k, wO - 1) * ld + min(c0 + c, n - 1)];
-    }
     v4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
@@ -767,51 +795,43 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
           p2[ii][jj][v] = T(0);
           p3[ii][jj][v] = T(0);
         }
-#pragma unroll
-    for (int t = 0; t < kLA; ++t) {
-      const int e = tid + t * NT;
-      const int i = e / kKC, k = e % kKC;
-      cplx<T> v = pa[t];
-      if (!(r0 + i < n && k < wO)) v.re = v.im = T(0);
-      As[0][i * AP + k] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < kLB; ++t) {
-      const int e = tid + t * NT;
-      const int k = e / kTile, c = e % kTile;
-      cplx<T> v = pb[t];
-      if (!(k < wO && c0 + c < n)) v.re = v.im = T(0);
-      Bsh[0][k * BP + c] = v;
-    }
+    gload(0);
+    lstore(0, 0);
     __syncthreads();
 
-    // the MFMAs of one K chunk from LDS buffer buf
+    // the MFMAs of one K chunk from LDS buffer buf; operands of the next
+    // k-step are read before the current k-step's products (ping-pong)
     auto mfma_chunk = [&](int buf) {
       const cplx<T>* as = As[buf];
       const cplx<T>* bs = Bsh[buf];
+      cplx<T> a[2][2], b[2][2];
 #pragma unroll
-      for (int k = 0; k < kKC; k += 4) {
-        T ar[2], ai[2], as_[2], br[2], bi[2], bs_[2];
+      for (int ii = 0; ii < 2; ++ii) a[0][ii] = as[(32 * wr + 16 * ii + li) * AP + lk];
 #pragma unroll
-        for (int ii = 0; ii < 2; ++ii) {
-          const cplx<T> a = as[(32 * wr + 16 * ii + li) * AP + k + lk];
-          ar[ii] = a.re;
-          ai[ii] = a.im;
-          as_[ii] = a.re + a.im;
+      for (int jj = 0; jj < 2; ++jj) b[0][jj] = bs[lk * BP + 32 * wc + 16 * jj + li];
+#pragma unroll
+      for (int s = 0; s < kKC / 4; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < kKC / 4) {
+          const int k = 4 * (s + 1);
+#pragma unroll
+          for (int ii = 0; ii < 2; ++ii)
+            a[cur ^ 1][ii] = as[(32 * wr + 16 * ii + li) * AP + k + lk];
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj)
+            b[cur ^ 1][jj] = bs[(k + lk) * BP + 32 * wc + 16 * jj + li];
         }
+        T as_[2], bs_[2];
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-          const cplx<T> b = bs[(k + lk) * BP + 32 * wc + 16 * jj + li];
-          br[jj] = b.re;
-          bi[jj] = b.im;
-          bs_[jj] = b.re + b.im;
-        }
+        for (int ii = 0; ii < 2; ++ii) as_[ii] = a[cur][ii].re + a[cur][ii].im;
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) bs_[jj] = b[cur][jj].re + b[cur][jj].im;
 #pragma unroll
         for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj) {
-            p1[ii][jj] = Mfma<T>::run(ar[ii], br[jj], p1[ii][jj]);
-            p2[ii][jj] = Mfma<T>::run(ai[ii], bi[jj], p2[ii][jj]);
+            p1[ii][jj] = Mfma<T>::run(a[cur][ii].re, b[cur][jj].re, p1[ii][jj]);
+            p2[ii][jj] = Mfma<T>::run(a[cur][ii].im, b[cur][jj].im, p2[ii][jj]);
             p3[ii][jj] = Mfma<T>::run(as_[ii], bs_[jj], p3[ii][jj]);
           }
       }
@@ -819,50 +839,11 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
 
     for (int kc = 0; kc + 1 < nch; ++kc) {
       const int buf = kc & 1;
-      const int kb = (kc + 1) * kKC;
-#pragma unroll
-      for (int t = 0; t < kLA; ++t) {
-        const int e = tid + t * NT;
-        const int i = e / kKC, k = e % kKC;
-        pa[t] = xm[(size_t)min(r0 + i, n - 1) * ld + J0 + min(kb + k, wO - 1)];
-      }
-#pragma unroll
-      for (int t = 0; t < kLB; ++t) {
-        const int e = tid + t * NT;
-        const int k = e / kTile, c = e % kTile;
-        pb[t] = bm[(size_t)min(kb + k, wO - 1) * ld + min(c0 + c, n - 1)];
-      }
+      gload((kc + 1) * kKC);
       mfma_chunk(buf);
-#pragma unroll
-      for (int t = 0; t < kLA; ++t) {
-        const int e = tid + t * NT;
-        const int i = e / kKC, k = e % kKC;
-        cplx<T> v = pa[t];
-        if (!(r0 + i < n && kb + k < wO)) v.re = v.im = T(0);
-        As[buf ^ 1][i * AP + k] = v;
-      }
-#pragma unroll
-      for (int t = 0; t < kLB; ++t) {
-        const int e = tid + t * NT;
-        const int k = e / kTile, c = e % kTile;
-        cplx<T> v = pb[t];
-        if (!(kb + k < wO && c0 + c < n)) v.re = v.im = T(0);
-        Bsh[buf ^ 1][k * BP + c] = v;
-      }
+      lstore((kc + 1) * kKC, buf ^ 1);
       __syncthreads();
     }
-    // last chunk, with the C tile's loads in flight
-    cplx<T> cv[2][2][4];
-#pragma unroll
-    for (int ii = 0; ii < 2; ++ii)
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1);
-          const int col = min(c0 + 32 * wc + 16 * jj + li, n - 1);
-          cv[ii][jj][v] = xm[(size_t)row * ld + col];
-        }
     mfma_chunk((nch - 1) & 1);
     __syncthreads();   // LDS free for this workgroup's next item
 #pragma unroll
@@ -876,10 +857,11 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
           if (row < n && col < n) {
             const int rc = rcv[ii][v];
             const bool keep = !(rc >= J0 && rc < J0 + wO);
+            const cplx<T> cv = xm[(size_t)row * ld + col];
             cplx<T> c;
             const T q1 = p1[ii][jj][v], q2 = p2[ii][jj][v];
-            c.re = (q1 - q2) + (keep ? cv[ii][jj][v].re : T(0));
-            c.im = ((p3[ii][jj][v] - q1) - q2) + (keep ? cv[ii][jj][v].im : T(0));
+            c.re = (q1 - q2) + (keep ? cv.re : T(0));
+            c.im = ((p3[ii][jj][v] - q1) - q2) + (keep ? cv.im : T(0));
             xm[(size_t)row * ld + col] = c;
           }
         }

@@ -125,8 +125,8 @@ SIGNATURES = {
     "fk_batch_iterate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                         _ip, _ip, _dp]),
     "fk_batch_timings": (ctypes.c_int, [_vp, _dp]),
-    "fk_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int, _ip, _ip,
-                                         ctypes.POINTER(Tuning)]),
+    "fk_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         _ip, _ip, ctypes.POINTER(Tuning)]),
 }
 
 _lib = None
@@ -511,15 +511,16 @@ class Batch:
         self._check(self._lib.fk_batch_set_tuning(self._h, ctypes.byref(t)),
                     "fk_batch_set_tuning")
 
-    def autotune(self, max_bytes=24 * 2 ** 30):
-        """Schedule per contour size (fk_batch_autotune): list of dicts with
-        n_c and the tuning fields."""
+    def autotune(self, max_bytes=24 * 2 ** 30, only_nc=0):
+        """Schedule per contour size (fk_batch_autotune; only_nc > 0: that size
+        alone, merged into the table): list of dicts with n_c and the tuning
+        fields of every class in the table."""
         cap = self.n
         ncls = ctypes.c_int()
         ncs = (ctypes.c_int * cap)()
         tun = (Tuning * cap)()
-        self._check(self._lib.fk_batch_autotune(self._h, float(max_bytes), cap,
-                                                ctypes.byref(ncls), ncs, tun),
+        self._check(self._lib.fk_batch_autotune(self._h, float(max_bytes), int(only_nc),
+                                                cap, ctypes.byref(ncls), ncs, tun),
                     "fk_batch_autotune")
         return [dict(n_c=ncs[q], **tun[q].as_dict()) for q in range(ncls.value)]
 

@@ -100,7 +100,7 @@ class WarmStart:
 
 
 def field_sweep_data(cont, us, es, n_eps, n_ebar, tol, rows_per_run, seed=0,
-                     max_iter=80, log=None):
+                     max_iter=80, log=None, u_rows=None):
     """Converged Sigma along field sweeps E = es[0], es[1], ... for every U
     (each field started from the previous one's Sigma, the first from zero),
     all U of one field solved together in one fk_batch.  Returns device tensors
@@ -146,6 +146,8 @@ def field_sweep_data(cont, us, es, n_eps, n_ebar, tol, rows_per_run, seed=0,
                                   xs, D_IN)
                     c.ws_targets(prev[i], new[i], idx, rows_per_run, sigma_scale(u), ts)
                     row += rows_per_run
+                    if u_rows is not None:
+                        u_rows.append(np.full(rows_per_run, u, dtype=np.float32))
         dt_s = time.perf_counter() - t0
         stats.append(dict(E=float(e), iters=[int(v) for v in r["iters"]],
                           converged=ok, seconds=dt_s))
@@ -157,14 +159,36 @@ def field_sweep_data(cont, us, es, n_eps, n_ebar, tol, rows_per_run, seed=0,
     return x[:row], t[:row], stats
 
 
-def train(x, t, steps=(12000, 8000, 4000), lrs=(1e-3, 3e-4, 1e-4), batch=4096,
-          seed=0, log=None):
-    """Adam on the sampled pairs (minibatches drawn by the library); the targets
-    are divided by their RMS first (host arithmetic on a copy)."""
+def target_stats(t, u_of_row=None):
+    """Percentiles of |t| and, per U range, the RMS of the targets (a host
+    summary of the training set)."""
+    th = np.abs(t.astype(np.float64)).ravel()
+    out = dict(p50=float(np.percentile(th, 50)), p90=float(np.percentile(th, 90)),
+               p99=float(np.percentile(th, 99)), p999=float(np.percentile(th, 99.9)),
+               max=float(th.max()), rms=float(np.sqrt(np.mean(th ** 2))))
+    if u_of_row is not None:
+        for lo, hi in ((0.0, 0.75), (0.75, 1.5), (1.5, 2.0), (2.0, 3.0)):
+            m = (u_of_row >= lo) & (u_of_row < hi)
+            if m.any():
+                out[f"rms_U{lo}-{hi}"] = float(np.sqrt(np.mean(t[m].astype(np.float64) ** 2)))
+    return out
+
+
+def train(x, t, steps=(12000, 8000, 4000), lrs=(3e-4, 1e-4, 3e-5), batch=4096,
+          seed=0, log=None, clip=8.0):
+    """Adam on the sampled pairs (minibatches drawn by the library).  The
+    targets are scaled by a robust size (the RMS of those within 20 times the
+    median magnitude) and clipped at +-clip of it (host arithmetic on a copy):
+    a few pairs with changes far beyond the typical one (the largest U near
+    field resonances) otherwise dominate the squared loss."""
     torch = _torch()
-    th = t.cpu().numpy()
-    t_rms = float(np.sqrt(np.mean(th.astype(np.float64) ** 2)))
-    tn = torch.from_numpy((th / t_rms).astype(np.float32)).cuda()
+    th = t.cpu().numpy().astype(np.float64)
+    a = np.abs(th)
+    core = a[a <= 20.0 * np.median(a) + 1e-30]
+    t_rms = float(np.sqrt(np.mean(core ** 2)))
+    tn = torch.from_numpy(np.clip(th / t_rms, -clip, clip).astype(np.float32)).cuda()
+    if log:
+        log(f"targets: scale {t_rms:.4g}, clipped rows {np.mean(np.abs(th / t_rms) > clip):.2e}")
     ws = WarmStart(t_rms=t_rms, seed=seed)
     hist = []
     for k, (n, lr) in enumerate(zip(steps, lrs)):
@@ -323,7 +347,7 @@ def _main(argv=None):
     tr.add_argument("--tol", type=float, default=1e-6)
     tr.add_argument("--rows", type=int, default=4096)
     tr.add_argument("--steps", type=int, nargs=3, default=[12000, 8000, 4000])
-    tr.add_argument("--lrs", type=float, nargs=3, default=[1e-3, 3e-4, 1e-4])
+    tr.add_argument("--lrs", type=float, nargs=3, default=[3e-4, 1e-4, 3e-5])
     tr.add_argument("--batch", type=int, default=4096)
     tr.add_argument("--seed", type=int, default=1)
     ev = sub.add_parser("evaluate", help="compare starts on unseen (U, E)")
@@ -346,20 +370,23 @@ def _main(argv=None):
     if a.cmd == "train":
         torch = _torch()
         rng = np.random.default_rng(a.seed)
-        xs, ts, stats = [], [], []
+        xs, ts, stats, u_rows = [], [], [], []
         t0 = time.perf_counter()
         for cont, n_u, ur in zip(TRAIN_CONTOURS, a.n_u, (a.u_range, a.u_range_fine)):
             us = np.sort(rng.uniform(ur[0], ur[1], n_u))
             log(f"contour dt={cont['dt']}: {n_u} values of U")
             x, t, st = field_sweep_data(cont, list(us), list(FIELDS), a.gh, a.gh, a.tol,
                                         a.rows, seed=int(rng.integers(1 << 31)),
-                                        max_iter=100, log=log)
+                                        max_iter=100, log=log, u_rows=u_rows)
             xs.append(x)
             ts.append(t)
             stats.append(dict(dt=cont["dt"], U=[float(u) for u in us], fields=st))
         x, t = torch.cat(xs), torch.cat(ts)
         gen_s = time.perf_counter() - t0
         log(f"data: {x.shape[0]} rows in {gen_s:.0f} s")
+        tstats = target_stats(t.cpu().numpy(), np.repeat(np.concatenate(u_rows), 2)
+                              .reshape(-1, 2) if u_rows else None)
+        log(f"target statistics: {tstats}")
         t0 = time.perf_counter()
         ws, hist = train(x, t, steps=tuple(a.steps), lrs=tuple(a.lrs), batch=a.batch,
                          seed=a.seed, log=log)
@@ -370,8 +397,9 @@ def _main(argv=None):
         with open(os.path.splitext(a.out)[0] + "_train.json", "w") as f:
             json.dump(dict(runs=runs, pairs=pairs, rows=int(x.shape[0]), gen_s=gen_s,
                            train_s=time.perf_counter() - t0, t_rms=ws.t_rms,
-                           loss_first=float(hist[0]),
+                           loss_first=float(np.mean(hist[:100])),
                            loss_last=float(np.mean(hist[-100:])), gh=a.gh, tol=a.tol,
+                           target_stats=tstats, lrs=list(a.lrs), steps=list(a.steps),
                            sweeps=stats), f, indent=1)
         log(f"saved {a.out}: {runs} runs, {pairs} pairs")
     else:

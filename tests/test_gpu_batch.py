@@ -182,6 +182,8 @@ def test_batch_autotune_per_size_class(lib):
     plan (one size class per chunk) give the results of the default plan."""
     print("case: batch autotune per N_c class", flush=True)
     with lib.Batch(INSTANCES) as b, lib.Batch(INSTANCES) as ref:
+        one = b.autotune(max_bytes=64 * 2 ** 20, only_nc=150)
+        assert [c["n_c"] for c in one] == [150]
         cls = b.autotune(max_bytes=64 * 2 ** 20)
         assert sorted(c["n_c"] for c in cls) == [73, 150, 200]
         assert all(c["tile_rows"] in (64, 128) and c["batch"] >= 1 and c["trials"] >= 2
