@@ -86,6 +86,16 @@ fk_status fk_gauss_hermite(int n, double* x, double* w);
  * z and W (each 2*N_c doubles, interleaved) may be NULL to query sizes. */
 fk_status fk_contour_build(const fk_contour* c, int* dims, double* z, double* W);
 
+/* Extrapolation to zero time step (Sec. II, the accuracy discussion of the
+ * results: Lagrange polynomials in dt through results at several steps):
+ * out[e] = sum_k w_k values[k * len + e], w_k = prod_{m != k} h_m / (h_m - h_k),
+ * the value at h = 0 of the polynomial of degree n_steps - 1 through
+ * (steps[k], values[k][e]).  values: n_steps rows of len doubles (complex data
+ * as interleaved (re, im), len doubling); host arrays.  FK_EINVAL for
+ * n_steps < 1, a step that is not finite and positive, or two equal steps. */
+fk_status fk_extrapolate_to_zero(int n_steps, const double* steps, int len,
+                                 const double* values, double* out);
+
 /* Status code name, e.g. "FK_ESINGULAR". */
 const char* fk_status_string(fk_status s);
 

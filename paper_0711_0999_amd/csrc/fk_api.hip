@@ -176,6 +176,29 @@ extern "C" fk_status fk_contour_build(const fk_contour* c, int* dims, double* z,
   return FK_OK;
 }
 
+extern "C" fk_status fk_extrapolate_to_zero(int n_steps, const double* steps, int len,
+                                            const double* values, double* out) {
+  if (n_steps < 1 || len < 0 || !steps || (len > 0 && (!values || !out)))
+    return FK_EINVAL;
+  for (int k = 0; k < n_steps; ++k) {
+    if (!std::isfinite(steps[k]) || !(steps[k] > 0.0)) return FK_EINVAL;
+    for (int m = 0; m < k; ++m)
+      if (steps[m] == steps[k]) return FK_EINVAL;
+  }
+  // w_k = prod_{m != k} h_m / (h_m - h_k): the value at h = 0 of the
+  // interpolating polynomial through (h_k, f_k) is sum_k w_k f_k
+  std::vector<double> w(n_steps, 1.0);
+  for (int k = 0; k < n_steps; ++k)
+    for (int m = 0; m < n_steps; ++m)
+      if (m != k) w[k] *= steps[m] / (steps[m] - steps[k]);
+  for (int e = 0; e < len; ++e) {
+    double acc = 0.0;
+    for (int k = 0; k < n_steps; ++k) acc += w[k] * values[(size_t)k * len + e];
+    out[e] = acc;
+  }
+  return FK_OK;
+}
+
 extern "C" const char* fk_status_string(fk_status s) {
   switch (s) {
     case FK_OK: return "FK_OK";

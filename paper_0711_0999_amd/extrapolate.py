@@ -7,10 +7,9 @@ multi-instance sweep (uneven N_c in shared batched launches, fk_batch); the
 current j(t), the filling n(t), the zeroth moment m0(t) and the equal-time
 spectral moments mu0, mu1, mu2 (fk_equal_time_moments, on the coarse times
 3..N_t - 4 of the coarsest grid) are read on the coarsest time grid, and their
-value at h = 0 is the Lagrange combination
-sum_k w_k f_k with w_k = prod_{m != k} h_m / (h_m - h_k).  The extrapolation is
-host arithmetic on a few vectors of N_t values; every DMFT step runs in the
-library's kernels.
+value at h = 0 is the Lagrange combination sum_k w_k f_k with w_k =
+prod_{m != k} h_m / (h_m - h_k) (fk_extrapolate_to_zero).  Every DMFT step
+and the combination run in the library; this module arranges the calls.
 """
 import numpy as np
 
@@ -18,14 +17,10 @@ from . import fkdmft
 
 
 def lagrange_weights(hs):
-    """w_k with sum_k w_k f(h_k) = p(0) for the polynomial p through the points."""
-    hs = np.asarray(hs, dtype=np.float64)
-    w = np.ones(len(hs))
-    for k in range(len(hs)):
-        for m in range(len(hs)):
-            if m != k:
-                w[k] *= hs[m] / (hs[m] - hs[k])
-    return w
+    """w_k with sum_k w_k f(h_k) = p(0) for the polynomial p through the points
+    (the combination's weights, from the library: the unit vectors' images)."""
+    n = len(hs)
+    return fkdmft.extrapolate_to_zero(hs, list(np.eye(n)))
 
 
 def step_sweep(t_min, t_max, beta, steps, model, tol=1e-10, max_iter=200,
@@ -57,7 +52,7 @@ def step_sweep(t_min, t_max, beta, steps, model, tol=1e-10, max_iter=200,
             mu = c.moments(np.arange(3, nc - 3) * s)
             per[h] = dict(j=j[::s][:nc], n=n[::s][:nc], m0=m0[::s][:nc], mu=mu)
     w = lagrange_weights(steps)
-    ext = {q: sum(w[k] * per[h][q] for k, h in enumerate(steps))
+    ext = {q: fkdmft.extrapolate_to_zero(steps, [per[h][q] for h in steps])
            for q in ("j", "n", "m0", "mu")}
     return dict(t=t_coarse, t_mu=t_coarse[3:nc - 3], per_step=per, extrapolated=ext,
                 weights=w, iters=[int(v) for v in r["iters"]])

@@ -59,6 +59,7 @@ SIGNATURES = {
     "fk_gauss_hermite": (ctypes.c_int, [ctypes.c_int, _dp, _dp]),
     "fk_contour_build": (ctypes.c_int, [ctypes.POINTER(Contour), _ip, _dp, _dp]),
     "fk_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fk_extrapolate_to_zero": (ctypes.c_int, [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp]),
     "fk_create": (ctypes.c_int, [ctypes.POINTER(Contour), ctypes.POINTER(Model),
                                  _vp, ctypes.POINTER(_vp)]),
     "fk_destroy": (ctypes.c_int, [_vp]),
@@ -164,6 +165,24 @@ def gauss_hermite(n):
     if s != FK_OK:
         raise FkError(s, f"gauss_hermite({n})")
     return x, w
+
+
+def extrapolate_to_zero(steps, values):
+    """fk_extrapolate_to_zero: values[k] (arrays of one shape, real or complex)
+    at the steps[k]; returns their extrapolation to step 0."""
+    hs = np.ascontiguousarray(steps, dtype=np.float64)
+    arrs = [np.asarray(v) for v in values]
+    cplx = any(np.iscomplexobj(a) for a in arrs)
+    shape = arrs[0].shape
+    rows = [np.ascontiguousarray(a, dtype=np.complex128 if cplx else np.float64).view(np.float64)
+            .ravel() for a in arrs]
+    data = np.ascontiguousarray(np.stack(rows))
+    out = np.zeros(data.shape[1])
+    s = library().fk_extrapolate_to_zero(len(hs), _dptr(hs), data.shape[1], _dptr(data),
+                                         _dptr(out))
+    if s != FK_OK:
+        raise FkError(s, "extrapolate_to_zero")
+    return (out.view(np.complex128) if cplx else out).reshape(shape)
 
 
 def contour_build(t_min, t_max, dt, dtau, beta):

@@ -188,3 +188,20 @@ def test_impurity_update_single_inversion_identity(convention, w1):
     cinv1 = x @ np.linalg.inv(np.eye(n) + y @ x)
     new_r1 = -h * s + w1 * (1 - w1) * (d0 - d1) ** 2 * (s @ cinv1 @ s)
     np.testing.assert_allclose(new_r1 / w[None, :], ref, rtol=1e-10, atol=1e-10)
+
+
+def test_extrapolate_to_zero_reproduces_polynomials(lib):
+    """fk_extrapolate_to_zero (host): through k steps it returns the value at
+    step 0 of any polynomial of degree < k exactly, elementwise, for real and
+    complex data; invalid steps are refused."""
+    hs = [0.2, 0.1, 0.05]
+    t = np.linspace(-1.0, 1.0, 7)
+    c0, c1, c2 = np.sin(t), np.cos(t) + 0.5j * t, t ** 2 - 1j
+    vals = [c0 + c1 * h + c2 * h * h for h in hs]
+    got = lib.extrapolate_to_zero(hs, vals)
+    assert np.max(np.abs(got - c0)) < 1e-13
+    real = lib.extrapolate_to_zero(hs[:2], [np.array([1 + h, 2 - 3 * h]) for h in hs[:2]])
+    assert np.allclose(real, [1.0, 2.0], atol=1e-14) and real.dtype == np.float64
+    for bad in ([0.1, 0.1], [0.1, -0.2], [0.1, float("nan")]):
+        with pytest.raises(lib.FkError):
+            lib.extrapolate_to_zero(bad, [np.zeros(3)] * len(bad))
