@@ -103,7 +103,7 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
                              int c0, int cw, unsigned char* smem) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int NCB = CW / 16, NRW = kPW / NCB;
-  constexpr int RB = 16 * NRW >= 64 ? 1 : 64 / (16 * NRW);
+  constexpr int RB = 1;
   constexpr int TRW = 16 * RB * NRW;
   static_assert(NCB * NRW == kPW && TRW <= kNB + kTile, "waves");
   constexpr int KP = KW + 1, CP = CW + 1;
@@ -140,26 +140,32 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
   const int wr = wave / NCB, wc = wave % NCB;
   const int li = lane & 15, lk = lane >> 4;
   const int col = 16 * wc + li;
-  for (int r0 = 0; r0 < m; r0 += TRW) {
-    __syncthreads();
-    cplx<T> mv[kLM];
+  // the tile's M values, its rows' rowcol entries and C values; the next
+  // tile's are loaded while the current one is multiplied (the tiles' rows
+  // are distinct, and the M columns are not written here)
+  cplx<T> mv[kLM];
+  int nrc[RB][4];
+  cplx<T> ncv[RB][4];
+  auto load_tile = [&](int t0) {
 #pragma unroll
     for (int t = 0; t < kLM; ++t) {
       const int e = tid + t * kPanelThreads;
       const int i = e / KW, l = e % KW;
-      mv[t] = x[(size_t)rows[min(r0 + i, m - 1)] * ld + j0 + min(l, w - 1)];
+      mv[t] = x[(size_t)rows[min(t0 + i, m - 1)] * ld + j0 + min(l, w - 1)];
     }
-    int rid[RB][4], rcv[RB][4];
-    cplx<T> cv[RB][4];
 #pragma unroll
     for (int ii = 0; ii < RB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int e = r0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
-        rid[ii][v] = rows[min(e, m - 1)];
-        rcv[ii][v] = rowcol[rid[ii][v]];
-        cv[ii][v] = x[(size_t)rid[ii][v] * ld + c0 + min(col, cw - 1)];
+        const int e = t0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
+        const int r = rows[min(e, m - 1)];
+        nrc[ii][v] = rowcol[r];
+        ncv[ii][v] = x[(size_t)r * ld + c0 + min(col, cw - 1)];
       }
+  };
+  load_tile(0);
+  for (int r0 = 0; r0 < m; r0 += TRW) {
+    __syncthreads();
 #pragma unroll
     for (int t = 0; t < kLM; ++t) {
       const int e = tid + t * kPanelThreads;
@@ -172,15 +178,18 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
     // formed from three real ones (Gauss) as in the trailing update:
     // P1 = Re a Re b, P2 = Im a Im b, P3 = (Re a + Im a)(Re b + Im b),
     // Re = P1 - P2, Im = P3 - P1 - P2, and C added afterwards
+    cplx<T> cv[RB][4];
 #pragma unroll
     for (int ii = 0; ii < RB; ++ii)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int e = r0 + 16 * (RB * wr + ii) + Mfma<T>::drow(lk, v);
         const bool keep = e < m && col < cw &&
-                          !(rcv[ii][v] >= j0 && rcv[ii][v] < j0 + w);
+                          !(nrc[ii][v] >= j0 && nrc[ii][v] < j0 + w);
+        cv[ii][v] = ncv[ii][v];
         if (!keep) cv[ii][v].re = cv[ii][v].im = T(0);
       }
+    if (r0 + TRW < m) load_tile(r0 + TRW);
     v4 p1[RB], p2[RB], p3[RB];
 #pragma unroll
     for (int ii = 0; ii < RB; ++ii)
@@ -209,7 +218,7 @@ __device__ __forceinline__ void cross_update(cplx<T>* __restrict__ x, int ld,
           cplx<T> c;
           c.re = (q1 - q2) + cv[ii][v].re;
           c.im = ((p3[ii][v] - q1) - q2) + cv[ii][v].im;
-          x[(size_t)rid[ii][v] * ld + c0 + col] = c;
+          x[(size_t)rows[e] * ld + c0 + col] = c;
         }
       }
   }
@@ -411,31 +420,44 @@ __device__ __forceinline__ void factor_panel(cplx<T>* __restrict__ x, int ld, in
       }
       const int src0 = b0 & 15;          // lane holding column b0 of the row
       const bool hi = b0 >= 16;          // ... in its second value
+      // kRU groups of four rows per wave and trip: their loads are issued
+      // together, so a wave waits for memory once per kRU groups (the rows
+      // of a trip are distinct; each is read and written by one lane group)
+      constexpr int kRU = 4, kStep = 4 * kPW;
 #pragma unroll 1
-      for (int e0 = 4 * wave; e0 < m; e0 += 4 * kPW) {
-        const int e = e0 + rr;
-        const int r = rows[min(e, m - 1)];
-        const cplx<T> va = x[(size_t)r * ld + c0 + min(ca, cw - 1)];
-        const cplx<T> vb = x[(size_t)r * ld + c0 + min(cb, cw - 1)];
-        bool isp = false;
+      for (int e0 = 4 * wave; e0 < m; e0 += kStep * kRU) {
+        int r[kRU];
+        cplx<T> va[kRU], vb[kRU];
 #pragma unroll
-        for (int l = 0; l < IB; ++l) isp |= (pv0[l] == r);
-        cplx<T> acca = va, accb = vb;
-        if (isp) acca.re = acca.im = accb.re = accb.im = T(0);
-        const cplx<T> src = hi ? vb : va;
+        for (int u = 0; u < kRU; ++u) r[u] = rows[min(e0 + kStep * u + rr, m - 1)];
 #pragma unroll
-        for (int l = 0; l < IB; ++l) {
-          if (l < iw) {
-            cplx<T> mm;
-            mm.re = __shfl(src.re, src0 + l, 16);
-            mm.im = __shfl(src.im, src0 + l, 16);
-            cfma(acca, mm, boa[l]);
-            cfma(accb, mm, bob[l]);
-          }
+        for (int u = 0; u < kRU; ++u) {
+          va[u] = x[(size_t)r[u] * ld + c0 + min(ca, cw - 1)];
+          vb[u] = x[(size_t)r[u] * ld + c0 + min(cb, cw - 1)];
         }
-        if (e < m) {
-          if (sta) x[(size_t)r * ld + c0 + ca] = acca;
-          if (stb) x[(size_t)r * ld + c0 + cb] = accb;
+#pragma unroll
+        for (int u = 0; u < kRU; ++u) {
+          const int e = e0 + kStep * u + rr;
+          bool isp = false;
+#pragma unroll
+          for (int l = 0; l < IB; ++l) isp |= (pv0[l] == r[u]);
+          cplx<T> acca = va[u], accb = vb[u];
+          if (isp) acca.re = acca.im = accb.re = accb.im = T(0);
+          const cplx<T> src = hi ? vb[u] : va[u];
+#pragma unroll
+          for (int l = 0; l < IB; ++l) {
+            if (l < iw) {
+              cplx<T> mm;
+              mm.re = __shfl(src.re, src0 + l, 16);
+              mm.im = __shfl(src.im, src0 + l, 16);
+              cfma(acca, mm, boa[l]);
+              cfma(accb, mm, bob[l]);
+            }
+          }
+          if (e < m) {
+            if (sta) x[(size_t)r[u] * ld + c0 + ca] = acca;
+            if (stb) x[(size_t)r[u] * ld + c0 + cb] = accb;
+          }
         }
       }
     }
