@@ -269,11 +269,15 @@ typedef struct {
 } fk_tuning;
 
 /* Time candidate schedules on this context's own point matrices (current
- * Sigma): every tile height x batch sizes up to max_bytes of device memory (the
- * budget, its half and quarter, and one to three times the device's compute
- * unit count) x look-ahead on/off; each candidate inverts one batch once for warm-up and
- * once timed, the estimate scales to all points.  Applies and returns the
- * fastest.  keep = 0 frees the inversion buffers afterwards. */
+ * Sigma): every tile height x batch sizes within max_bytes of device memory
+ * (the points split evenly into k batches for the smallest k the budget allows
+ * and the next three, the budget's quarter, and one to three times the
+ * device's compute unit count) x look-ahead on/off.  Each candidate inverts one
+ * batch once for warm-up and once timed; the estimate is that time times the
+ * number of batches.  The three fastest are timed again afterwards (the first
+ * trials on a cold device run fast) and the choice uses those times only.
+ * Applies and returns the fastest.  keep = 0 frees the inversion buffers
+ * afterwards. */
 fk_status fk_autotune(fk_ctx* ctx, double max_bytes, int keep, fk_tuning* best);
 fk_status fk_set_tuning(fk_ctx* ctx, const fk_tuning* t);
 fk_status fk_get_tuning(const fk_ctx* ctx, fk_tuning* t);
@@ -391,9 +395,12 @@ fk_status fk_ws_targets(fk_ctx* ctx, const double* sigma_prev_dev,
                         const double* sigma_new_dev, const long long* idx_dev,
                         long long rows, double scale, float* t_dev);
 /* Sets the context's Sigma to Sigma_prev + y / scale (y: N_c^2 rows of 2;
- * sigma_prev_dev may be the context's own Sigma buffer). */
+ * sigma_prev_dev may be the context's own Sigma buffer).  keep_pre_field != 0:
+ * the pairs whose two contour points both lie before the field is switched on
+ * (real time <= 0 on the real branches; every imaginary-branch point) keep
+ * Sigma_prev (causality: there the solution does not depend on E). */
 fk_status fk_ws_apply(fk_ctx* ctx, const double* sigma_prev_dev,
-                      const float* y_dev, double scale);
+                      const float* y_dev, double scale, int keep_pre_field);
 /* The self-consistency loop of fk_iterate started from the context's current
  * Sigma (a proposed start, e.g. from fk_ws_apply) and judged by the plain
  * iteration: the start is kept if its first iteration changes Sigma by at most

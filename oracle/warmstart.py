@@ -62,10 +62,25 @@ def targets(sigma_prev, sigma_new, idx, scale):
     return np.stack([d.real, d.imag], axis=1)
 
 
-def apply(sigma_prev, y, scale):
-    """Sigma_prev + y / scale, y holding (Re, Im) rows of all pairs in order."""
+def apply(sigma_prev, y, scale, pre_field=None):
+    """Sigma_prev + y / scale, y holding (Re, Im) rows of all pairs in order.
+    pre_field (optional, N_c booleans): the contour points before the field is
+    switched on; pairs of two such points keep Sigma_prev."""
     n = sigma_prev.shape[0]
-    return sigma_prev + (y[:, 0] + 1j * y[:, 1]).reshape(n, n) / scale
+    out = sigma_prev + (y[:, 0] + 1j * y[:, 1]).reshape(n, n) / scale
+    if pre_field is not None:
+        keep = np.outer(pre_field, pre_field)
+        out[keep] = sigma_prev[keep]
+    return out
+
+
+def pre_field_points(z, n_t):
+    """Contour points before the field (Sec. II: the vector potential is zero
+    up to t = 0): real time <= 0 on the two real branches (the first n_t and
+    the next n_t points), and every point of the imaginary branch."""
+    z = np.asarray(z)
+    idx = np.arange(len(z))
+    return np.where(idx < 2 * n_t, z.real <= 1e-12, True)
 
 
 def randomized_singular_values(a, omega):

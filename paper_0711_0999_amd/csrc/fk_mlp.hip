@@ -329,11 +329,20 @@ __global__ void k_targets(const c64* __restrict__ sprev, const c64* __restrict__
 }
 
 // Sigma = Sigma_prev + y / scale at every pair (y: n*n rows of 2)
+// Sigma = Sigma_prev + y / scale; with keep_pre the pairs whose contour points
+// both lie before the field is switched on (upper-branch indices below a,
+// lower-branch indices from b on, every imaginary-branch index) keep Sigma_prev.
 __global__ void k_apply(const c64* __restrict__ sprev, const float* __restrict__ y,
-                        size_t total, double inv_scale, c64* __restrict__ sigma) {
+                        int n, int a, int b, int keep_pre, double inv_scale,
+                        c64* __restrict__ sigma) {
+  const size_t total = (size_t)n * n;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x)
-    sigma[e] = c64{sprev[e].re + inv_scale * y[2 * e], sprev[e].im + inv_scale * y[2 * e + 1]};
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const bool pre = keep_pre && (i < a || i >= b) && (j < a || j >= b);
+    sigma[e] = pre ? sprev[e]
+                   : c64{sprev[e].re + inv_scale * y[2 * e], sprev[e].im + inv_scale * y[2 * e + 1]};
+  }
 }
 
 }  // namespace fk
@@ -833,13 +842,20 @@ extern "C" fk_status fk_ws_targets(fk_ctx* c, const double* sigma_prev_dev,
 }
 
 extern "C" fk_status fk_ws_apply(fk_ctx* c, const double* sigma_prev_dev,
-                                 const float* y_dev, double scale) {
+                                 const float* y_dev, double scale, int keep_pre_field) {
   if (!c || !sigma_prev_dev || !y_dev || !(scale != 0.0)) return FK_EINVAL;
-  const size_t total = (size_t)c->ci.n_c * c->ci.n_c;
+  const int n = c->ci.n_c, n_t = c->ci.n_t;
+  // the branches run t_min -> t_max and back; the field acts from t = 0 on
+  // (a small tolerance for the rounding of t_min + j dt at t = 0)
+  const double tiny = 1e-9 * c->c.dt;
+  int a = 0, b = 2 * n_t;
+  while (a < n_t && c->ci.zr[a] <= tiny) ++a;
+  while (b > n_t && c->ci.zr[b - 1] <= tiny) --b;
+  const size_t total = (size_t)n * n;
   const int grid = (int)std::min<size_t>((total + 255) / 256, 8192);
   hipLaunchKernelGGL(k_apply, dim3(grid), dim3(256), 0, c->st,
-                     reinterpret_cast<const c64*>(sigma_prev_dev), y_dev, total,
-                     1.0 / scale, c->d_sigma);
+                     reinterpret_cast<const c64*>(sigma_prev_dev), y_dev, n, a, b,
+                     keep_pre_field ? 1 : 0, 1.0 / scale, c->d_sigma);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   return e == hipSuccess ? FK_OK : FK_EDEVICE;

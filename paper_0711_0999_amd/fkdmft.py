@@ -115,7 +115,7 @@ SIGNATURES = {
                                       ctypes.c_int]),
     "fk_ws_targets": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_longlong,
                                      ctypes.c_double, _vp]),
-    "fk_ws_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double]),
+    "fk_ws_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int]),
     "fk_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Contour),
                                        ctypes.POINTER(Model), ctypes.POINTER(_vp)]),
     "fk_batch_destroy": (ctypes.c_int, [_vp]),
@@ -448,9 +448,10 @@ class Context:
             None if idx_dev is None else idx_dev.data_ptr(), rows, float(scale),
             t_dev.data_ptr()), "fk_ws_targets")
 
-    def ws_apply(self, sigma_prev_dev, y_dev, scale):
+    def ws_apply(self, sigma_prev_dev, y_dev, scale, keep_pre_field=False):
         self._check(self._lib.fk_ws_apply(self._h, sigma_prev_dev.data_ptr(),
-                                          y_dev.data_ptr(), float(scale)), "fk_ws_apply")
+                                          y_dev.data_ptr(), float(scale),
+                                          int(bool(keep_pre_field))), "fk_ws_apply")
 
     def timings(self):
         out = np.zeros(7)

@@ -84,8 +84,10 @@ class WarmStart:
         assert list(f["dims"]) == [D_IN, WIDTH, DEPTH, D_OUT, RANK]
         return cls(params=f["params"], t_rms=float(f["t_rms"]))
 
-    def propose(self, ctx, cont, sigma_prev, u, e, bf16=True):
-        """Sets ctx's Sigma to the proposed start; returns the time it took (s)."""
+    def propose(self, ctx, cont, sigma_prev, u, e, bf16=True, keep_pre_field=False):
+        """Sets ctx's Sigma to the proposed start; returns the time it took (s).
+        keep_pre_field: pairs of contour points before the field is switched on
+        keep the previous field's values (the network's change applies after)."""
         torch = _torch()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -94,7 +96,7 @@ class WarmStart:
         x = torch.empty((n * n, D_IN), dtype=torch.float32, device="cuda")
         ctx.ws_features(sigma_prev, g, None, n * n, PREV_GAIN * sigma_scale(u), x, D_IN)
         y = self.net.forward(x, bf16=bf16)
-        ctx.ws_apply(sigma_prev, y, sigma_scale(u) / self.t_rms)
+        ctx.ws_apply(sigma_prev, y, sigma_scale(u) / self.t_rms, keep_pre_field)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -255,7 +257,9 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
             out["equilibrium_solve_iters"] = r["iters"]
     glocs = {}
     starts = ([s for s in starts if s != "network_mixed" or mixed]
-              + [f"network_accept{a:g}" for a in also_accept])
+              + [f"network_accept{a:g}" for a in also_accept]
+              + ([f"network_keep_accept{a:g}" for a in also_accept]
+                 if "network_keep" in starts else []))
     assert starts[0] == "zero", "the Sigma = 0 run defines the fixed point"
     fixed = None
     for start in starts:
@@ -271,7 +275,13 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
                 c.set_sigma(equil)
                 r = c.iterate(max_iter, tol=tol)
             else:
-                out[f"{start}_propose_s"] = ws.propose(c, cont, prev, u, e)
+                keep = start.startswith("network_keep")
+                out[f"{start}_propose_s"] = ws.propose(c, cont, prev, u, e,
+                                                       keep_pre_field=keep)
+                if fixed is not None and start == "network_keep":
+                    s0 = c.get_sigma()
+                    out["start_err_keep"] = [float(np.max(np.abs(s0 - fixed))),
+                                             float(np.sqrt(np.mean(np.abs(s0 - fixed) ** 2)))]
                 if fixed is not None and start == "network":
                     s0 = c.get_sigma()
                     p0 = prev.cpu().numpy()
@@ -282,8 +292,8 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
                     out["start_err_regions"] = _error_regions(c, cont, p0, s0, fixed)
                 prec = fkdmft.FK_MIXED if start == "network_mixed" else fkdmft.FK_FP64
                 acc = accept
-                if start.startswith("network_accept"):
-                    acc = float(start[len("network_accept"):])
+                if "_accept" in start:
+                    acc = float(start[start.index("_accept") + len("_accept"):])
                 r = c.iterate_judged(prev, max_iter, tol=tol, accept=acc, precision=prec)
                 out[f"{start}_outcome"] = r["outcome"]
             torch.cuda.synchronize()
@@ -303,6 +313,10 @@ def compare_starts(ws, cont, u, e, n_eps, n_ebar, tol, max_iter=200, accept=0.5,
             + (f", network+mixed {out.get('network_mixed_iters')}" if mixed else "")
             + "".join(f", accept {a:g}: {out[f'network_accept{a:g}_iters']}"
                       for a in also_accept)
+            + (f", kept pre-field {out['network_keep_iters']} "
+               f"(outcome {out['network_keep_outcome']})" if "network_keep" in starts else "")
+            + "".join(f", kept pre-field accept {a:g}: {out[f'network_keep_accept{a:g}_iters']}"
+                      for a in also_accept if "network_keep" in starts)
             + f"; start error max/rms previous {out.get('start_err_previous')}, "
             f"network {out.get('start_err_network')}; spread {out['gloc_spread']:.1e}")
     return out

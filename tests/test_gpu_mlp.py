@@ -142,6 +142,13 @@ def test_features_targets_and_apply(lib, use_idx):
         y = inputs.random_rows(n * n, 2, seed=18)
         c.ws_apply(dev(sp), dev(y), 0.7)
         assert relerr(c.get_sigma(), ows.apply(sp, y.astype(np.float64), 0.7)) < 1e-12
+        # the pairs before the field (t <= 0 and the imaginary branch) keep Sigma_prev
+        pre = ows.pre_field_points(z, c.n_t)
+        assert 0 < pre.sum() < n
+        c.ws_apply(dev(sp), dev(y), 0.7, keep_pre_field=True)
+        got = c.get_sigma()
+        assert relerr(got, ows.apply(sp, y.astype(np.float64), 0.7, pre)) < 1e-12
+        assert np.array_equal(got[np.outer(pre, pre)], sp[np.outer(pre, pre)])
         with pytest.raises(lib.FkError):
             c.ws_features(dev(sp), glob, di, rows, 0.7, x, 64)   # d_in too small
 

@@ -917,3 +917,25 @@ def test_contour_imaginary_branch_matches_matsubara_solver():
         errs.append(np.max(np.abs(g_contour - matsubara.g_tau(beta, giw, k * dtau))))
     assert errs[-1] < 2e-3
     assert 0.35 < errs[1] / errs[0] < 0.6 and 0.35 < errs[2] / errs[1] < 0.6
+
+
+def test_warm_start_pre_field_mask_by_hand():
+    """Pairs of contour points before the field (Sec. II: the vector potential
+    vanishes up to t = 0) on the contour t in [-1, 1], dt = 0.5, beta = 1,
+    dtau = 0.5: upper -1, -0.5, 0, 0.5; lower 1, 0.5, 0, -0.5; imaginary
+    -1, -1 - 0.5i.  Before the field: indices 0, 1, 2, 6, 7, 8, 9.  The masked
+    proposal keeps Sigma_prev exactly on the pairs of two such points and adds
+    y / scale everywhere else."""
+    from oracle import warmstart
+    z, _ = contour.points(-1.0, 1.0, 0.5, 0.5, 1.0)
+    pre = warmstart.pre_field_points(z, 4)
+    assert list(np.nonzero(pre)[0]) == [0, 1, 2, 6, 7, 8, 9]
+    sp = np.arange(100).reshape(10, 10) * (1 + 0.5j)
+    y = np.tile([2.0, -4.0], (100, 1))
+    out = warmstart.apply(sp, y, 2.0, pre)
+    for i in range(10):
+        for j in range(10):
+            want = sp[i, j] if (i in (0, 1, 2, 6, 7, 8, 9) and j in (0, 1, 2, 6, 7, 8, 9)) \
+                else sp[i, j] + 1 - 2j
+            assert out[i, j] == want
+    assert np.array_equal(warmstart.apply(sp, y, 2.0), sp + 1 - 2j)
