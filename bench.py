@@ -37,11 +37,9 @@ PEAK_HBM_GBS = 8000.0
 # fk::k_update<double, 2>, 757-matrix batches of the C2 workload), from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs summarized under profiles/, each
 # scaled by the same counter's reading for a plain 256 MiB copy.  Reported only
-# for that kernel, batch size and schedule ("paired": K = 256 updates); None
-# until the counters have been taken on the current kernel.  Measured:
-# FETCH_SIZE 33869690 KiB x 2.00 + WRITE_SIZE 31117324 KiB x 1.00 per launch.
-PROFILED_TRAFFIC = {"kernel": "fk::k_update<double, 2>", "batch": 757,
-                    "bytes_per_launch": (2.00 * 33869690.2 + 1.00 * 31117324.2) * 1024}
+# for that kernel, batch size and schedule (groups of four outer blocks, K up
+# to 512); None until the counters have been taken on the current kernel.
+PROFILED_TRAFFIC = None
 
 # Each complex product of the trailing update is formed from three real ones
 # (Gauss), so its matrix cores execute 6 of the 8 real flops per complex

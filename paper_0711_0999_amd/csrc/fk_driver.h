@@ -91,14 +91,15 @@ template <typename T> void batch_free(Batch<T>& b) {
 
 // Update work items of matrix m (n rows, tiles of tr_rows rows) for outer
 // step S and phase q, and their algorithmic flops (8 per complex multiply-add:
-// rows x columns x K per tile).  The phases of step S (block_role):
-//   q = 0  single or first block of a pair: the next block's columns, K = block
-//          S; second block: the first block's columns, M = block S (side rows
-//          kNBO..), bringing that block up to date
-//   q = 1  second block: the next block's columns, both blocks' transforms
-//   q = 2  the trailing update of every other column: single block with its
-//          own transform, second block with both (K = 256); nothing for a
-//          first block (delayed until its pair is factored)
+// rows x columns x K per tile).  With block S at position p of the group that
+// starts at block g0 = S - p (block_pos), the phases of step S:
+//   q = 0  p = 0: the next block's columns, K = block S;  p > 0: the columns
+//          of the group's earlier blocks g0 .. S-1, M = block S (side rows
+//          p kNBO ..), bringing them up to date
+//   q = 1  p > 0: the next block's columns, the transforms of blocks g0 .. S
+//   q = 2  last block of its group: the trailing update of every column
+//          outside blocks g0 .. S+1 with the group's transforms (K up to
+//          kBRows); nothing for the other blocks (delayed)
 // Items are ordered in bands of kSwz column tiles, rows outer within a band,
 // so the workgroups in flight on one XCD (consecutive items) share both their
 // pivot-block rows and their B columns in its L2.
@@ -107,32 +108,32 @@ inline double push_tiles(std::vector<TileItem>& it, int m, int n, int tr_rows, i
                          int q) {
   const int nout = (n + kNBO - 1) / kNBO;
   if (S >= nout) return 0.0;
-  const int role = block_role(n, S);
+  const int p = block_pos(n, S), g0 = S - p;
   auto width = [&](int blk) { return std::min(kNBO, n - blk * kNBO); };
+  int group_w = 0;               // columns of blocks g0 .. S
+  for (int blk = g0; blk <= S; ++blk) group_w += width(blk);
   const bool next = S + 1 < nout;
   int jb = S, kw = width(S), b0 = 0;
   int lo = 0, hi = -1;        // q < 2: the column blocks [lo, hi] to update
-  int x0 = S, x1 = S + 1;     // q = 2: the column blocks [x0, x1] left out
+  int x0 = g0, x1 = S + 1;    // q = 2: the column blocks [x0, x1] left out
   if (q == 0) {
-    if (role == 2) {
-      lo = hi = S - 1;
-      b0 = kNBO;
+    if (p > 0) {
+      lo = g0;
+      hi = S - 1;
+      b0 = p * kNBO;
     } else if (next) {
       lo = hi = S + 1;
     }
   } else if (q == 1) {
-    if (role == 2 && next) {
+    if (p > 0 && next) {
       lo = hi = S + 1;
-      jb = S - 1;
-      kw = width(S - 1) + width(S);
+      jb = g0;
+      kw = group_w;
     }
   } else {
-    if (role == 1) return 0.0;
-    if (role == 2) {
-      jb = S - 1;
-      kw = width(S - 1) + width(S);
-      x0 = S - 1;
-    }
+    if (!block_last(n, S)) return 0.0;
+    jb = g0;
+    kw = group_w;
   }
   const int nt = (n + kTile - 1) / kTile, ntr = (n + tr_rows - 1) / tr_rows;
   std::vector<int> cols;

@@ -22,10 +22,10 @@
 //   update  every other column tile: C <- mask_P(C) + M B, a batched complex
 //           GEMM on the matrix cores (three real products per complex one),
 //           double-buffered K chunks in LDS, two workgroups per CU.  Blocks
-//           are applied in pairs (K = 256, see block_role): the first block
-//           of a pair updates only the next block's columns, the second
-//           brings the first block's columns up to date and then applies both
-//           transforms to all other columns at once.
+//           are applied in groups of kGroup (K up to 512, see block_pos): each
+//           block of a group brings the group's earlier blocks' columns up to
+//           date and updates the next block's columns; the last one applies
+//           all the group's transforms to every other column at once.
 // The host runs the update of the next block's columns first; with the
 // look-ahead schedule it factors that block on a second stream while the big
 // update of the current step runs.

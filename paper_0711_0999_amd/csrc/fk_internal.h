@@ -42,9 +42,13 @@ struct TileItem {
   short pad;
 };
 
+#ifndef FK_GROUP_BLOCKS
+#define FK_GROUP_BLOCKS 4
+#endif
 constexpr int kNB = 64;          // inner panel width (columns)
 constexpr int kNBO = 128;        // outer block: two inner panels
-constexpr int kBRows = 2 * kNBO; // side buffer rows: two outer blocks' pivot rows
+constexpr int kGroup = FK_GROUP_BLOCKS;  // outer blocks per delayed trailing update
+constexpr int kBRows = kGroup * kNBO;    // side buffer rows: one group's pivot rows
 constexpr int kPhases = 3;       // update launches per outer step (push_tiles)
 constexpr int kTile = 64;        // trailing-update tile (rows = cols)
 constexpr int kKC = 16;          // K chunk of the trailing update
@@ -53,23 +57,34 @@ constexpr int kPanelThreads = 512;
 constexpr int kGemmThreads = 256;
 constexpr int kMaxN = 5120;      // largest matrix the inversion supports
 
-// Outer blocks are applied to the columns outside them one or two at a time.
-// Counted from the last block, blocks pair up ((L-1, L), (L-3, L-2), ...; L =
-// nouter - 1); with an odd count block 0 stays single.  A pair's trailing
-// update is delayed until both blocks are factored and then applies the two
-// transforms at once (K up to 2 kNBO): with M1, M2 the transformed identity
-// columns and B1, B2 the gathered pivot rows of the two blocks,
-//   C <- mask(C) + [M1' | M2] [B1; B2],  M1' = mask(M1) + M2 B2[:, block 1],
-// which equals the two steps one after the other.  Role of block S of an
-// n-row matrix: 0 single, 1 first of a pair, 2 second of a pair.
-__host__ __device__ inline int block_role(int n, int S) {
+// Outer blocks are applied to the columns outside them in groups of up to
+// kGroup blocks, counted from the last block ((L-g+1 .. L), (L-2g+1 .. L-g),
+// ...; L = nouter - 1, g = kGroup); the first nouter mod g blocks form a
+// shorter group.  A group's trailing update is delayed until all its blocks
+// are factored and then applies their transforms at once (K up to kBRows):
+// with M_i the transformed identity columns of the group's blocks and B_i
+// their gathered pivot rows (values before the group's first step outside
+// the group),
+//   C <- mask(C) + [M_1' | ... | M_g] [B_1; ...; B_g],
+// where M_i' is M_i brought up to date by the transforms of the later blocks
+// of the group (each block, once factored, updates the earlier blocks'
+// columns: M <- mask(M) + M_p B_p), which equals the steps one after the
+// other.  Before block p of a group is factored its own columns receive the
+// transforms of the group's blocks before it in the same form.
+// Position of block S of an n-row matrix within its group (0 = first).
+__host__ __device__ inline int block_pos(int n, int S) {
+  const int r = ((n + kNBO - 1) / kNBO) % kGroup;
+  return S < r ? S : (S - r) % kGroup;
+}
+// Whether block S is the last of its group (its step runs the trailing update).
+__host__ __device__ inline bool block_last(int n, int S) {
   const int nout = (n + kNBO - 1) / kNBO;
-  if ((nout & 1) && S == 0) return 0;
-  return ((nout - 1 - S) & 1) == 0 ? 2 : 1;
+  const int r = nout % kGroup;
+  return S + 1 == nout || (S < r ? S == r - 1 : (S - r) % kGroup == kGroup - 1);
 }
 // First side-buffer row of block S's gathered pivot rows.
 __host__ __device__ inline int block_brow(int n, int S) {
-  return block_role(n, S) == 2 ? kNBO : 0;
+  return block_pos(n, S) * kNBO;
 }
 
 // Outer step S of the blocked in-place Gauss-Jordan inversion, pieces:
