@@ -799,13 +799,26 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
       for (int t = 0; t < kLB; ++t) Bsh[buf][(bk0 + BST * t) * BP + bc] = pb[t];
     };
 
+    // Edge tiles with at most 16 valid rows (or columns) use a strip layout:
+    // wave w multiplies the single 16 x 16 block at columns (rows) 16 w of
+    // the strip, a quarter of an interior tile's matrix-core work, instead of
+    // a 32 x 32 quarter that lies mostly outside the matrix.  The choice is
+    // the same for the whole workgroup.
+    const int edge = (n - r0 <= 16) ? 1 : ((n - c0 <= 16) ? 2 : 0);
+    const int er0 = edge == 2 ? 16 * wave : 0;   // strip block origin (rows)
+    const int ec0 = edge == 1 ? 16 * wave : 0;   // strip block origin (columns)
+    // waves whose strip block lies inside the tile (all of them for a
+    // 64 x 64 tile; the first four of a 128-row tile's eight in a row strip)
+    const bool eact = edge == 1 ? ec0 < kTile : er0 < TR;
     // pivot-row mask of the rows this lane writes
     int rcv[2][4];
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        rcv[ii][v] = rowcol[min(r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v), n - 1)];
+      for (int v = 0; v < 4; ++v) {
+        const int rr = edge ? er0 + 16 * ii : 32 * wr + 16 * ii;
+        rcv[ii][v] = rowcol[min(r0 + rr + Mfma<T>::drow(lk, v), n - 1)];
+      }
     v4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
@@ -859,14 +872,41 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
       }
     };
 
-    for (int kc = 0; kc + 1 < nch; ++kc) {
-      const int buf = kc & 1;
-      gload((kc + 1) * kKC);
-      mfma_chunk(buf);
-      lstore((kc + 1) * kKC, buf ^ 1);
-      __syncthreads();
+    // strip layout: one 16 x 16 block per wave, accumulated in p*[0][0]
+    auto mfma_chunk_edge = [&](int buf) {
+      if (!eact) return;
+      const cplx<T>* as = As[buf];
+      const cplx<T>* bs = Bsh[buf];
+#pragma unroll
+      for (int s = 0; s < kKC / 4; ++s) {
+        const int k = 4 * s;
+        const cplx<T> a = as[(er0 + li) * AP + k + lk];
+        const cplx<T> b = bs[(k + lk) * BP + ec0 + li];
+        p1[0][0] = Mfma<T>::run(a.re, b.re, p1[0][0]);
+        p2[0][0] = Mfma<T>::run(a.im, b.im, p2[0][0]);
+        p3[0][0] = Mfma<T>::run(a.re + a.im, b.re + b.im, p3[0][0]);
+      }
+    };
+
+    if (!edge) {
+      for (int kc = 0; kc + 1 < nch; ++kc) {
+        const int buf = kc & 1;
+        gload((kc + 1) * kKC);
+        mfma_chunk(buf);
+        lstore((kc + 1) * kKC, buf ^ 1);
+        __syncthreads();
+      }
+      mfma_chunk((nch - 1) & 1);
+    } else {
+      for (int kc = 0; kc + 1 < nch; ++kc) {
+        const int buf = kc & 1;
+        gload((kc + 1) * kKC);
+        mfma_chunk_edge(buf);
+        lstore((kc + 1) * kKC, buf ^ 1);
+        __syncthreads();
+      }
+      mfma_chunk_edge((nch - 1) & 1);
     }
-    mfma_chunk((nch - 1) & 1);
     __syncthreads();   // LDS free for this workgroup's next item
 #pragma unroll
     for (int ii = 0; ii < 2; ++ii)
@@ -874,8 +914,9 @@ __global__ __launch_bounds__(128 * WR, 4 / WR) void k_update(
       for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = r0 + 32 * wr + 16 * ii + Mfma<T>::drow(lk, v);
-          const int col = c0 + 32 * wc + 16 * jj + li;
+          if (edge && (ii || jj || !eact)) continue;
+          const int row = r0 + (edge ? er0 : 32 * wr + 16 * ii) + Mfma<T>::drow(lk, v);
+          const int col = c0 + (edge ? ec0 : 32 * wc + 16 * jj) + li;
           if (row < n && col < n) {
             const int rc = rcv[ii][v];
             const bool keep = !(rc >= J0 && rc < J0 + wO);
