@@ -39,7 +39,10 @@ PEAK_HBM_GBS = 8000.0
 # scaled by the same counter's reading for a plain 256 MiB copy.  Reported only
 # for that kernel, batch size and schedule (groups of four outer blocks, K up
 # to 512); None until the counters have been taken on the current kernel.
-PROFILED_TRAFFIC = None
+# Measured: FETCH_SIZE 69358020 KiB x 2.00 + WRITE_SIZE 26671992 KiB x 1.00
+# per launch.
+PROFILED_TRAFFIC = {"kernel": "fk::k_update<double, 2>", "batch": 757,
+                    "bytes_per_launch": (2.00 * 69358019.7 + 1.00 * 26671992.2) * 1024}
 
 # Each complex product of the trailing update is formed from three real ones
 # (Gauss), so its matrix cores execute 6 of the 8 real flops per complex
@@ -393,11 +396,14 @@ def main():
     # textbook 2 N^3 of a real inversion, four real products per complex one)
     flops_iter = 8.0 * n ** 3 * npts
     inversion_tflops = flops_iter * args.steps / (step_ms * 1e-3) / 1e12
-    # dominant kernel: the trailing update of each outer block (pair), timed
-    # per launch.  Primary rate: the flops its matrix cores execute (three real
-    # products per complex one, 6 real flops per complex multiply-add), which
-    # the peak bounds; beside it the algorithmic rate (8 per complex
-    # multiply-add), which exceeds the peak once the kernel passes 3/4 of it
+    # dominant kernel: the trailing update of each group of outer blocks,
+    # timed per launch.  Primary rate: the flops its matrix cores execute
+    # (three real products per complex one, 6 real flops per complex
+    # multiply-add), which the peak bounds; beside it the algorithmic rate (8
+    # per complex multiply-add), which exceeds the peak once the kernel passes
+    # 3/4 of it
+    if kc["ms"] <= 0 or kc["launches"] == 0:
+        raise RuntimeError("the kernel clock recorded no trailing-update launch")
     alg_tflops = kc["flop"] / (kc["ms"] * 1e-3) / 1e12
     achieved = EXECUTED_PER_ALGORITHMIC * alg_tflops
     peak = PEAK_FP32_TFLOPS if args.mixed else PEAK_FP64_TFLOPS

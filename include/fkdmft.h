@@ -243,13 +243,14 @@ fk_status fk_low_iterations(const fk_ctx* ctx, int* n);
  * inversion kernel launches, out[6] summed duration of the step kernels. */
 fk_status fk_timings(const fk_ctx* ctx, double* out7);
 
-/* Timing of the dominant kernel, the trailing update of each 128-column outer
- * block of the batched Gauss-Jordan inversion in fk_compute_gloc: with the
- * clock on (fk_set_kernel_clock(ctx, 1), which also zeroes it) every such
- * launch is bracketed by HIP events on the context stream.  out3: summed
- * launch duration in ms, number of launches, summed algorithmic flops of those
- * launches (8 n * cols * K per matrix: n rows, cols outside the two blocks being
- * factored, K the block width). */
+/* Timing of the dominant kernel, the trailing update of each group of
+ * 128-column outer blocks of the batched Gauss-Jordan inversion in
+ * fk_compute_gloc (FP64 or complex64): with the clock on
+ * (fk_set_kernel_clock(ctx, 1), which also zeroes it) every such launch is
+ * bracketed by HIP events on the context stream.  out3: summed launch duration
+ * in ms, number of launches, summed algorithmic flops of those launches
+ * (8 n * cols * K per matrix: n rows, cols outside the group's blocks and the
+ * next block, K the group's width, up to 512). */
 fk_status fk_set_kernel_clock(fk_ctx* ctx, int on);
 fk_status fk_kernel_clock(const fk_ctx* ctx, double* out3);
 

@@ -404,7 +404,9 @@ fk_status lattice_step_mixed(fk_ctx* c, double* ir_out) {
     HIPCHK(c, launch_build<float>(c->d_sigt, c->tab, k0, nmat, b.x, b.stride, b.ld,
                                   n, c->st));
     HIPCHK(c, hipEventRecord(c->ev[1], c->st));
-    HIPCHK(c, batch_invert<float>(b, nmat, c->st, c->aux, &launches, &c->ev[6]));
+    Aux ax = c->aux;
+    ax.clk = c->clk.on ? &c->clk : nullptr;
+    HIPCHK(c, batch_invert<float>(b, nmat, c->st, ax, &launches, &c->ev[6]));
     HIPCHK(c, hipEventRecord(c->ev[2], c->st));
     if (ir == 0) {
       HIPCHK(c, hipEventRecord(c->ev[3], c->st));
@@ -445,6 +447,7 @@ fk_status lattice_step_mixed(fk_ctx* c, double* ir_out) {
     HIPCHK(c, hipEventRecord(c->ev[4], c->st));
     s = check_status(c, b.status, nmat, k0, "complex64 inversion");
     if (s != FK_OK) return s;
+    if (c->clk.on) clock_collect(c->clk);
     c->times[0] += elapsed(c->ev[0], c->ev[1]);
     c->times[1] += elapsed(c->ev[1], c->ev[2]);
     c->times[2] += elapsed(c->ev[2], c->ev[3]);
