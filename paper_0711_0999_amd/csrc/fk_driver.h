@@ -332,9 +332,9 @@ struct Aux {
   KernelClock* clk = nullptr;
 };
 
-// Invert matrices 0..nmat-1 of the batch in place (permuted storage).  The
-// next outer block is factored on the side stream while the big update of
-// the current block runs on st.  ev_steps (nullable) brackets the kernels.
+// Invert matrices 0..nmat-1 of the batch in place (permuted storage).  With
+// the look-ahead schedule the next outer block is factored on the side stream
+// while the trailing update of the current group runs on st.  ev_steps (nullable) brackets the kernels.
 // For an uneven batch nmat must be b.cap and status is the caller's array
 // (indexed by the descriptors' status_idx, not cleared here).
 template <typename T>
@@ -366,8 +366,8 @@ hipError_t batch_invert(Batch<T>& b, int nmat, hipStream_t st, const Aux& ax,
         return e;
       ++nl;
     }
-    // the next block's columns (and, for the second block of a pair, the
-    // first block's columns before them), so that the next panel can start
+    // the group's earlier blocks' columns and the next block's columns, so
+    // that the next panel can start
     for (int q = 0; q < 2; ++q) {
       int cnt = 0;
       const TileItem* it = items_of(q, S, &cnt);
