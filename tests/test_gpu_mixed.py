@@ -58,3 +58,27 @@ def test_mixed_switching_loop_reaches_fp64_fixed_point(lib):
     ro = dmft.run(problem(w), 80, tol=1e-11)
     assert relerr(ctx.get_gloc(), ro["gloc"]) < 1e-8
     assert relerr(ctx.get_current()[1], ro["current"]) < 1e-8
+
+
+@pytest.mark.parametrize("tile_rows", [64, 128])
+def test_mixed_edge_tiles(lib, tile_rows):
+    """N_c = 258 = 4 x 64 + 2 = 2 x 128 + 2: the last row and column tiles of
+    every update hold two valid rows or columns (the strip layout of the
+    update kernel, for both tile heights) in the complex64 inversion; with two
+    FP64 refinement steps G_loc and j(t) reach the oracle to 1e-10."""
+    kw = dict(t_min=-3.0, t_max=3.2, dt=0.05, dtau=0.1, beta=1.0)
+    print(f"case: mixed edge tiles N_c=258 tile_rows={tile_rows}", flush=True)
+    ctx = lib.Context(U=1.5, E=2.0, n_eps=3, n_ebar=3, **kw)
+    assert ctx.n_c == 258
+    ctx.set_tuning(tile_rows=tile_rows, batch=0, lookahead=0)
+    sig = inputs.random_sigma(ctx.n_c, seed=23, scale=0.1)
+    ctx.set_sigma(sig)
+    go, jo, _ = dmft.lattice_only(dmft.Problem(u=1.5, e_field=2.0, n_eps=3, n_ebar=3,
+                                               **kw), sig)
+    ctx.set_refinement(0)
+    ctx.compute_gloc(lib.FK_MIXED)
+    assert 1e-9 < relerr(ctx.get_gloc(), go) < 1e-4
+    ctx.set_refinement(2)
+    ctx.compute_gloc(lib.FK_MIXED)
+    assert relerr(ctx.get_gloc(), go) < 1e-10
+    assert relerr(ctx.get_current()[1], jo) < 1e-10
