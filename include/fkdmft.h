@@ -86,6 +86,19 @@ fk_status fk_gauss_hermite(int n, double* x, double* w);
  * z and W (each 2*N_c doubles, interleaved) may be NULL to query sizes. */
 fk_status fk_contour_build(const fk_contour* c, int* dims, double* z, double* W);
 
+/* The schedule of the batched Gauss-Jordan inversion of the point matrices
+ * (the integrand of eq. g_loc, Sec. II), host logic only, for checking it
+ * against a plain inversion: outer blocks of 128 columns in groups of up to
+ * four counted from the last block; step S of an n x n matrix runs phases
+ * q = 0, 1, 2, each the update C <- mask(C) + M B with M the columns
+ * [128 jb, 128 jb + kw), B the side-buffer rows [b0, b0 + kw) (the gathered
+ * pivot rows of the group's blocks) and mask zeroing the rows pivoted in M's
+ * columns.  out6 = {jb, kw, b0, lo, hi, brow}: for q < 2 the column blocks
+ * lo .. hi (none if hi < lo), for q = 2 every column block outside lo .. hi
+ * (none if kw = 0); brow = first side-buffer row of block S's pivot rows.
+ * FK_EINVAL for n outside 1 .. 5120, S < 0 or q outside 0 .. 2. */
+fk_status fk_update_plan(int n, int S, int q, int* out6);
+
 /* Extrapolation to zero time step (Sec. II, the accuracy discussion of the
  * results: Lagrange polynomials in dt through results at several steps):
  * out[e] = sum_k w_k values[k * len + e], w_k = prod_{m != k} h_m / (h_m - h_k),

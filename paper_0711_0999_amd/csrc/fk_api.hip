@@ -176,6 +176,18 @@ extern "C" fk_status fk_contour_build(const fk_contour* c, int* dims, double* z,
   return FK_OK;
 }
 
+extern "C" fk_status fk_update_plan(int n, int S, int q, int* out6) {
+  if (n < 1 || n > kMaxN || S < 0 || q < 0 || q >= kPhases || !out6) return FK_EINVAL;
+  const PhasePlan pl = phase_plan(n, S, q);
+  out6[0] = pl.jb;
+  out6[1] = pl.kw;
+  out6[2] = pl.b0;
+  out6[3] = pl.lo;
+  out6[4] = pl.hi;
+  out6[5] = block_brow(n, S);
+  return FK_OK;
+}
+
 extern "C" fk_status fk_extrapolate_to_zero(int n_steps, const double* steps, int len,
                                             const double* values, double* out) {
   if (n_steps < 1 || len < 0 || !steps || (len > 0 && (!values || !out)))

@@ -104,37 +104,57 @@ template <typename T> void batch_free(Batch<T>& b) {
 // so the workgroups in flight on one XCD (consecutive items) share both their
 // pivot-block rows and their B columns in its L2.
 constexpr int kSwz = 8;
-inline double push_tiles(std::vector<TileItem>& it, int m, int n, int tr_rows, int S,
-                         int q) {
+// The transform and the column blocks of phase q of step S (see above):
+// M = columns [jb kNBO, jb kNBO + kw), B = side-buffer rows [b0, b0 + kw); for
+// q < 2 the column blocks lo .. hi (none if hi < lo), for q = 2 every block
+// outside lo .. hi (none if kw = 0).
+struct PhasePlan {
+  int jb, kw, b0, lo, hi;
+};
+inline PhasePlan phase_plan(int n, int S, int q) {
   const int nout = (n + kNBO - 1) / kNBO;
-  if (S >= nout) return 0.0;
+  PhasePlan pl{S, 0, 0, 0, -1};
+  if (S >= nout) return pl;
   const int p = block_pos(n, S), g0 = S - p;
   auto width = [&](int blk) { return std::min(kNBO, n - blk * kNBO); };
   int group_w = 0;               // columns of blocks g0 .. S
   for (int blk = g0; blk <= S; ++blk) group_w += width(blk);
   const bool next = S + 1 < nout;
-  int jb = S, kw = width(S), b0 = 0;
-  int lo = 0, hi = -1;        // q < 2: the column blocks [lo, hi] to update
-  int x0 = g0, x1 = S + 1;    // q = 2: the column blocks [x0, x1] left out
+  pl.kw = width(S);
   if (q == 0) {
     if (p > 0) {
-      lo = g0;
-      hi = S - 1;
-      b0 = p * kNBO;
+      pl.lo = g0;
+      pl.hi = S - 1;
+      pl.b0 = p * kNBO;
     } else if (next) {
-      lo = hi = S + 1;
+      pl.lo = pl.hi = S + 1;
     }
   } else if (q == 1) {
     if (p > 0 && next) {
-      lo = hi = S + 1;
-      jb = g0;
-      kw = group_w;
+      pl.lo = pl.hi = S + 1;
+      pl.jb = g0;
+      pl.kw = group_w;
     }
   } else {
-    if (!block_last(n, S)) return 0.0;
-    jb = g0;
-    kw = group_w;
+    if (!block_last(n, S)) {
+      pl.kw = 0;
+      return pl;
+    }
+    pl.jb = g0;
+    pl.kw = group_w;
+    pl.lo = g0;
+    pl.hi = S + 1;
   }
+  return pl;
+}
+inline double push_tiles(std::vector<TileItem>& it, int m, int n, int tr_rows, int S,
+                         int q) {
+  const int nout = (n + kNBO - 1) / kNBO;
+  if (S >= nout) return 0.0;
+  const PhasePlan pl = phase_plan(n, S, q);
+  if (q == 2 && pl.kw == 0) return 0.0;
+  const int jb = pl.jb, kw = pl.kw, b0 = pl.b0;
+  const int lo = pl.lo, hi = pl.hi, x0 = pl.lo, x1 = pl.hi;
   const int nt = (n + kTile - 1) / kTile, ntr = (n + tr_rows - 1) / tr_rows;
   std::vector<int> cols;
   for (int tc = 0; tc < nt; ++tc) {

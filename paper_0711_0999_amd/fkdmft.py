@@ -115,6 +115,7 @@ SIGNATURES = {
                                       ctypes.c_int]),
     "fk_ws_targets": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_longlong,
                                      ctypes.c_double, _vp]),
+    "fk_update_plan": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]),
     "fk_ws_apply": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int]),
     "fk_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Contour),
                                        ctypes.POINTER(Model), ctypes.POINTER(_vp)]),
@@ -183,6 +184,16 @@ def extrapolate_to_zero(steps, values):
     if s != FK_OK:
         raise FkError(s, "extrapolate_to_zero")
     return (out.view(np.complex128) if cplx else out).reshape(shape)
+
+
+def update_plan(n, S, q):
+    """fk_update_plan: the transform and column blocks of phase q of outer step
+    S of the batched inversion of an n x n matrix."""
+    out = (ctypes.c_int * 6)()
+    s = library().fk_update_plan(int(n), int(S), int(q), out)
+    if s != FK_OK:
+        raise FkError(s, "update_plan")
+    return dict(jb=out[0], kw=out[1], b0=out[2], lo=out[3], hi=out[4], brow=out[5])
 
 
 def contour_build(t_min, t_max, dt, dtau, beta):

@@ -205,3 +205,77 @@ def test_extrapolate_to_zero_reproduces_polynomials(lib):
     for bad in ([0.1, 0.1], [0.1, -0.2], [0.1, float("nan")]):
         with pytest.raises(lib.FkError):
             lib.extrapolate_to_zero(bad, [np.zeros(3)] * len(bad))
+
+
+def _gauss_jordan_by_plan(lib, a, nb=128):
+    """The blocked in-place Gauss-Jordan inversion in numpy, with the library's
+    own schedule (fk_update_plan): per outer block the columns are eliminated
+    one by one over all rows (pivot: largest |re| + |im| among rows not yet
+    pivoted), the block's pivot rows are copied to the side buffer, and the
+    three update phases of the plan are applied as C <- mask(C) + M B.  Rows
+    are never swapped: inv(A)[i][j] = X[piv[i]][rowcol[j]]."""
+    n = a.shape[0]
+    x = a.astype(np.complex128).copy()
+    piv = -np.ones(n, dtype=int)
+    rowcol = -np.ones(n, dtype=int)
+    side = np.zeros((8 * nb, n), dtype=np.complex128)
+    nout = (n + nb - 1) // nb
+    for s in range(nout):
+        j0, w = s * nb, min(nb, n - s * nb)
+        cols = slice(j0, j0 + w)
+        for c in range(j0, j0 + w):
+            key = np.abs(x[:, c].real) + np.abs(x[:, c].imag)
+            key[rowcol >= 0] = -1.0
+            p = int(np.argmax(key))
+            piv[c], rowcol[p] = p, c
+            inv = 1.0 / x[p, c]
+            q = x[p, cols] * inv
+            m = x[:, c].copy()
+            x[:, cols] -= np.outer(m, q)
+            x[p, cols] = q
+            x[:, c] = -m * inv
+            x[p, c] = inv
+        brow = lib.update_plan(n, s, 0)["brow"]
+        side[brow:brow + w] = x[piv[j0:j0 + w]]
+        for ph in range(3):
+            pl = lib.update_plan(n, s, ph)
+            blk = np.arange(n) // nb
+            if ph < 2:
+                take = (blk >= pl["lo"]) & (blk <= pl["hi"])
+            else:
+                take = ((blk < pl["lo"]) | (blk > pl["hi"])) & (pl["kw"] > 0)
+            if not take.any():
+                continue
+            m0, kw, b0 = pl["jb"] * nb, pl["kw"], pl["b0"]
+            keep = ~((rowcol >= m0) & (rowcol < m0 + kw))
+            x[:, take] = x[:, take] * keep[:, None] + x[:, m0:m0 + kw] @ side[b0:b0 + kw][:, take]
+    return x[piv][:, rowcol]
+
+
+@pytest.mark.parametrize("n", [100, 300, 520, 700, 1050, 1800])
+def test_update_plan_inverts(lib, n):
+    """The library's schedule of the batched inversion (outer blocks of 128
+    columns grouped from the last block, delayed trailing updates), applied in
+    numpy, gives the inverse: against numpy.linalg.inv for block counts that
+    leave every group shape (1, 3, 5, 6, 9 and 15 blocks, ragged last blocks)."""
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    got = _gauss_jordan_by_plan(lib, a)
+    ref = np.linalg.inv(a)
+    assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_update_plan_groups_and_errors(lib):
+    """Groups of up to four blocks counted from the last: at N_c = 1800 (15
+    blocks) the trailing updates run after blocks 2, 6, 10 and 14, with K = 384,
+    512, 512 and 392; invalid arguments are refused."""
+    trail = [(s, lib.update_plan(1800, s, 2)) for s in range(15)]
+    done = [(s, p["kw"], p["jb"]) for s, p in trail if p["kw"] > 0]
+    assert done == [(2, 384, 0), (6, 512, 3), (10, 512, 7), (14, 392, 11)]
+    p = lib.update_plan(1800, 5, 0)      # third block of the group 3 .. 6
+    assert (p["jb"], p["kw"], p["b0"], p["lo"], p["hi"], p["brow"]) == (5, 128, 256, 3, 4, 256)
+    p = lib.update_plan(1800, 5, 1)      # the next block with the group so far
+    assert (p["jb"], p["kw"], p["lo"], p["hi"]) == (3, 384, 6, 6)
+    for bad in ((0, 0, 0), (1800, -1, 0), (1800, 0, 3), (6000, 0, 0)):
+        with pytest.raises(lib.FkError):
+            lib.update_plan(*bad)
