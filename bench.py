@@ -493,6 +493,7 @@ def main():
                         + ("" if args.converge else
                            " (reduced grid; full-grid runs: --workload c2-converge)"),
                 "points": conv_kw["n_eps"] * conv_kw["n_ebar"], "tol": configs.C2_TOL}
+        out["config"]["converge_block_grid"] = conv["grid"]
         for name, p2 in (("fp64", fkdmft.FK_FP64), ("mixed_switch", fkdmft.FK_MIXED)):
             ctx2 = fkdmft.Context(stream=stream, **conv_kw)
             if args.converge:
